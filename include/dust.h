@@ -1,0 +1,183 @@
+/*
+ * dust.h -- C-ABI of libdust: dust-grain equilibrium temperatures and the
+ * resulting emission SED on an AMD MI355X (gfx950) GPU.
+ *
+ * The calculation is the one of Jonsson & Primack, "Accelerating Dust
+ * Temperature Calculations with Graphics Processing Units" (New Astronomy),
+ * Section 4: for every grid cell c and grain s (a species and size),
+ *
+ *   absorb   H[c,s] = sum_l J[c,l] C[s,l] dlam[l]                     (Eq. 6)
+ *   solve    T[c,s] such that sum_l C[s,l] dlam[l] B(lam_l, T) = H     (Eq. 7)
+ *   emit     L[c,l] = m[c] sum_s w[s] C[s,l] B(lam_l, T[c,s])          (Eqs. 8-10)
+ *
+ * with B the Planck function (Eq. 1), J the mean intensity of the radiation
+ * field, C the absorption cross-sections, w the number of grains per unit
+ * dust mass (the paper's n_s) and m the dust mass of the cell (m_d;c).
+ *
+ * Units: SI at the boundary (lam, dlam in m; C in m^2; grain size in m;
+ * J in W m^-2 m^-1 sr^-1).  H and L carry no factor 4 pi (both sides of
+ * Eq. 7 drop the same factor, so T is unaffected).
+ *
+ * Conventions shared by every call:
+ *  - Arrays are row-major.  C = cells, NL = wavelengths, S = grains.
+ *  - Grid tables (dust_grid_desc) are HOST float64 pointers, read only during
+ *    dust_plan_create; the caller keeps ownership.
+ *  - J, H, T, L, m_dust are DEVICE pointers on the device that was current
+ *    when the plan was created, 4-byte aligned; the caller owns them.
+ *    Leading dimensions (ldj, ldh, ldt, ldl) count elements and must be at
+ *    least the row width (NL for J and L, S for H and T).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
+ *    work: they neither allocate nor synchronise, except dust_plan_create,
+ *    dust_plan_destroy, dust_batch_create and dust_batch_destroy.
+ *  - Every argument is checked before any HIP call; a bad argument returns
+ *    DUST_EINVAL and the reason is available from dust_last_error().
+ *  - Numerical conditions are not errors.  They are counted in an optional
+ *    DEVICE dust_counters (zero it before the call; counts are added
+ *    atomically):
+ *      n_nonfinite     pairs whose H is NaN, infinite or negative -> T = NaN
+ *      n_unconverged   pairs where the iteration cap was reached
+ *                      (the last iterate is kept)
+ *      n_out_of_table  pairs of the mixed solve whose T lies outside the
+ *                      tabulated range (solved exactly instead)
+ *    H == 0 gives T = 0, and a grain at T = 0 emits nothing.
+ *  - Calls that share a plan may run concurrently on different streams.
+ */
+#ifndef DUST_H
+#define DUST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DUST_OK = 0,
+    DUST_EINVAL = -1,       /* invalid argument (nothing was enqueued) */
+    DUST_EUNSUPPORTED = -2, /* valid but outside what this library handles */
+    DUST_ENOMEM = -3,       /* device allocation failed */
+    DUST_EDEVICE = -4       /* a HIP runtime call failed */
+} dust_status;
+
+typedef enum {
+    /* FP32 throughout: FP32 MFMA heating, FP32 Newton on the exact sum of
+       Eq. 7 from the Eq. 11 guess, FP32 emission. */
+    DUST_PLAIN_FP32 = 0,
+    /* Mixed precision: heating on BF16 MFMA with hi+lo split operands and
+       FP32 accumulation; T from an FP64 table of ln P(ln T) per grain with
+       an FP64 Newton polish on its cubic Hermite interpolant; FP32 emission. */
+    DUST_MIXED = 1
+} dust_mode;
+
+/* One grid: its wavelength grid and grain set (host float64). */
+typedef struct {
+    int32_t n_lambda;      /* NL >= 1 */
+    int32_t n_grains;      /* S  >= 1 */
+    const double* lambda;  /* [NL] wavelengths (m), > 0, strictly increasing */
+    const double* dlambda; /* [NL] quadrature weights of the sums (m), >= 0 */
+    const double* c_abs;   /* [S][NL] absorption cross-sections (m^2), >= 0 */
+    const double* weight;  /* [S] grains per unit dust mass (n_s), >= 0 */
+    const double* size;    /* [S] grain radius (m), > 0; only steers the
+                              Eq. 11 initial guess of the FP32 Newton solve */
+} dust_grid_desc;
+
+/* Options; a zero field selects the default shown. */
+typedef struct {
+    int32_t mode;      /* dust_mode; default DUST_PLAIN_FP32 */
+    int32_t maxit;     /* plain: Newton iteration cap, default 50 */
+    double tol;        /* plain: stop when |P(T)/H - 1| <= tol, default 1e-5 */
+    int32_t ltab_n;    /* mixed: table points per grain, default 4096 (>= 16) */
+    int32_t reserved;  /* must be 0 */
+    double ltab_tmin;  /* mixed: lowest tabulated T (K), default 2.7 */
+    double ltab_tmax;  /* mixed: highest tabulated T (K), default 3000 */
+} dust_options;
+
+/* Device-side event counters (see the conventions above). */
+typedef struct {
+    int64_t n_nonfinite;
+    int64_t n_unconverged;
+    int64_t n_out_of_table;
+} dust_counters;
+
+/* Opaque, library-owned plan: the grid's derived device tables. */
+typedef struct dust_plan dust_plan;
+
+/* Build a plan on the current device: upload the grid, derive the kernel
+ * tables (the paper's first kernel, Section 4.1: C dlam per grain and
+ * wavelength, plus the emission weights and, for DUST_MIXED, the FP64
+ * power tables) and wait for them.  Allocates device memory. */
+dust_status dust_plan_create(const dust_grid_desc* grid, const dust_options* opt,
+                             dust_plan** out);
+
+/* Free a plan (waits for the device).  NULL is accepted. */
+dust_status dust_plan_destroy(dust_plan* plan);
+
+/* Re-derive the plan's tables on `stream` from its stored float64 grid
+ * (the same work dust_plan_create does, without allocating). */
+dust_status dust_plan_prepare(dust_plan* plan, void* stream);
+
+/* Query plan sizes: any pointer may be NULL. */
+dust_status dust_plan_info(const dust_plan* plan, int32_t* n_lambda,
+                           int32_t* n_grains, int32_t* mode);
+
+/* Eq. 6 (Section 4.2): H[c*ldh + s] for c < n_cells, s < S, FP32 output. */
+dust_status dust_absorb(dust_plan* plan, int64_t n_cells,
+                        const float* J, int64_t ldj,
+                        float* H, int64_t ldh, void* stream);
+
+/* Eq. 7 (Section 4.3): T[c*ldt + s] from H[c*ldh + s].  `counters` may be
+ * NULL. */
+dust_status dust_solve_T(dust_plan* plan, int64_t n_cells,
+                         const float* H, int64_t ldh,
+                         float* T, int64_t ldt,
+                         dust_counters* counters, void* stream);
+
+/* Eqs. 9-10 (Section 4.4): L[c*ldl + l] from T[c*ldt + s].  m_dust may be
+ * NULL (every cell has unit dust mass). */
+dust_status dust_emit_sed(dust_plan* plan, int64_t n_cells,
+                          const float* T, int64_t ldt, const float* m_dust,
+                          float* L, int64_t ldl, void* stream);
+
+/* Eqs. 6, 7, 9-10 in one launch per cell tile: H stays on chip and never
+ * reaches device memory.  Same results as absorb -> solve -> emit. */
+dust_status dust_run_fused(dust_plan* plan, int64_t n_cells,
+                           const float* J, int64_t ldj, const float* m_dust,
+                           float* T, int64_t ldt, float* L, int64_t ldl,
+                           dust_counters* counters, void* stream);
+
+/* Many independent grids in one persistent launch.  A batch binds plans and
+ * buffers once (host arrays of length n_grids; m_dust[g] may be NULL), builds
+ * the work list of (grid, cell tile) items ordered by cost, picks tile shapes
+ * with the autotuner when `autotune` is non-zero (timing candidate launches on
+ * the bound buffers, which it overwrites) and records one HIP graph.
+ * All plans must be DUST_MIXED plans of the current device. */
+typedef struct dust_batch dust_batch;
+
+dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids,
+                              const int64_t* n_cells,
+                              const float* const* J, const int64_t* ldj,
+                              const float* const* m_dust,
+                              float* const* T, const int64_t* ldt,
+                              float* const* L, const int64_t* ldl,
+                              dust_counters* counters, int32_t autotune,
+                              dust_batch** out);
+
+/* Replay the batch's graph on `stream` (allocates nothing). */
+dust_status dust_batch_launch(dust_batch* batch, void* stream);
+
+/* Tile configuration the batch uses (cells per tile), for reporting. */
+dust_status dust_batch_info(const dust_batch* batch, int32_t* cells_per_tile,
+                            int64_t* n_items);
+
+dust_status dust_batch_destroy(dust_batch* batch);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* dust_last_error(void);
+
+/* Library version string. */
+const char* dust_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,262 @@
+"""Python binding of libdust, the gfx950 dust-temperature library.
+
+Argument marshalling only: every step of the calculation runs in the HIP
+kernels of ``libdust.so`` behind the C-ABI declared in ``include/dust.h``.
+torch tensors serve as device buffers (their data pointers and the current
+HIP stream are passed through).  There is no CPU fallback: if the library is
+not built, or no GPU is present, calls raise.
+
+Section 4 of Jonsson & Primack (New Astronomy, "Accelerating Dust Temperature
+Calculations with Graphics Processing Units") defines the three steps:
+absorb (Eq. 6), solve (Eq. 7) and emit (Eqs. 9-10).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdust.so")
+
+DUST_OK, DUST_EINVAL, DUST_EUNSUPPORTED, DUST_ENOMEM, DUST_EDEVICE = 0, -1, -2, -3, -4
+PLAIN, MIXED = 0, 1
+_MODES = {"plain": PLAIN, "mixed": MIXED, PLAIN: PLAIN, MIXED: MIXED}
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("n_lambda", _i32), ("n_grains", _i32),
+                ("lambda_", _vp), ("dlambda", _vp), ("c_abs", _vp),
+                ("weight", _vp), ("size", _vp)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", _i32), ("maxit", _i32), ("tol", ctypes.c_double),
+                ("ltab_n", _i32), ("reserved", _i32),
+                ("ltab_tmin", ctypes.c_double), ("ltab_tmax", ctypes.c_double)]
+
+
+class DustError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdust error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def build():
+    """Compile libdust.so in-tree (hipcc, gfx950)."""
+    from . import builder
+    return builder.build()
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_0907_3768_amd.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    L.dust_last_error.restype = ctypes.c_char_p
+    L.dust_version.restype = ctypes.c_char_p
+    sigs = {
+        "dust_plan_create": [ctypes.POINTER(GridDesc), ctypes.POINTER(Options), ctypes.POINTER(_vp)],
+        "dust_plan_destroy": [_vp],
+        "dust_plan_prepare": [_vp, _vp],
+        "dust_plan_info": [_vp, _vp, _vp, _vp],
+        "dust_absorb": [_vp, _i64, _vp, _i64, _vp, _i64, _vp],
+        "dust_solve_T": [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp],
+        "dust_emit_sed": [_vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp],
+        "dust_run_fused": [_vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp],
+        "dust_batch_create": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
+                              ctypes.POINTER(_vp)],
+        "dust_batch_launch": [_vp, _vp],
+        "dust_batch_info": [_vp, _vp, _vp],
+        "dust_batch_destroy": [_vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.restype = st
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().dust_last_error().decode()
+
+
+def _check(code):
+    if code != DUST_OK:
+        raise DustError(code, last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _vp(stream)
+    return _vp(stream.cuda_stream)
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp(0)
+
+
+def _rows(t, width, name):
+    """(pointer, leading dimension) of a 2-D float32 CUDA tensor with unit column stride."""
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+    if t.dim() != 2 or t.stride(1) != 1 or t.shape[1] < width:
+        raise ValueError(f"{name} must be 2-D, row-major, with at least {width} columns")
+    return _vp(t.data_ptr()), t.stride(0) if t.shape[0] > 1 else max(t.shape[1], width)
+
+
+def new_counters(device="cuda"):
+    """A zeroed device dust_counters (int64 x 3: nonfinite, unconverged, out_of_table)."""
+    import torch
+    return torch.zeros(3, dtype=torch.int64, device=device)
+
+
+class Plan:
+    """A grid's device tables (dust_plan)."""
+
+    def __init__(self, grid, mode="plain", tol=0.0, maxit=0, ltab_n=0, ltab_tmin=0.0,
+                 ltab_tmax=0.0):
+        self._keep = [np.ascontiguousarray(a, dtype=np.float64)
+                      for a in (grid.lam, grid.dlam, grid.c_abs, grid.weight, grid.size)]
+        lam, dlam, cabs, w, a = self._keep
+        self.n_lambda = int(lam.shape[0])
+        self.n_grains = int(cabs.shape[0])
+        self.mode = _MODES[mode]
+        desc = GridDesc(self.n_lambda, self.n_grains, lam.ctypes.data, dlam.ctypes.data,
+                        cabs.ctypes.data, w.ctypes.data, a.ctypes.data)
+        opt = Options(self.mode, int(maxit), float(tol), int(ltab_n), 0, float(ltab_tmin),
+                      float(ltab_tmax))
+        h = _vp()
+        _check(lib().dust_plan_create(ctypes.byref(desc), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dust_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, stream=None):
+        _check(lib().dust_plan_prepare(self._h, _stream(stream)))
+
+    def _alloc(self, n, width, like):
+        import torch
+        return torch.empty((n, width), dtype=torch.float32, device=like.device)
+
+    def absorb(self, J, H=None, stream=None):
+        n = J.shape[0]
+        H = self._alloc(n, self.n_grains, J) if H is None else H
+        pj, ldj = _rows(J, self.n_lambda, "J")
+        ph, ldh = _rows(H, self.n_grains, "H")
+        _check(lib().dust_absorb(self._h, n, pj, ldj, ph, ldh, _stream(stream)))
+        return H
+
+    def solve(self, H, T=None, counters=None, stream=None):
+        n = H.shape[0]
+        T = self._alloc(n, self.n_grains, H) if T is None else T
+        ph, ldh = _rows(H, self.n_grains, "H")
+        pt, ldt = _rows(T, self.n_grains, "T")
+        _check(lib().dust_solve_T(self._h, n, ph, ldh, pt, ldt, _ptr(counters), _stream(stream)))
+        return T
+
+    def emit(self, T, m_dust=None, L=None, stream=None):
+        n = T.shape[0]
+        L = self._alloc(n, self.n_lambda, T) if L is None else L
+        pt, ldt = _rows(T, self.n_grains, "T")
+        pl, ldl = _rows(L, self.n_lambda, "L")
+        _check(lib().dust_emit_sed(self._h, n, pt, ldt, _ptr(m_dust), pl, ldl, _stream(stream)))
+        return L
+
+    def fused(self, J, m_dust=None, T=None, L=None, counters=None, stream=None):
+        n = J.shape[0]
+        T = self._alloc(n, self.n_grains, J) if T is None else T
+        L = self._alloc(n, self.n_lambda, J) if L is None else L
+        pj, ldj = _rows(J, self.n_lambda, "J")
+        pt, ldt = _rows(T, self.n_grains, "T")
+        pl, ldl = _rows(L, self.n_lambda, "L")
+        _check(lib().dust_run_fused(self._h, n, pj, ldj, _ptr(m_dust), pt, ldt, pl, ldl,
+                                    _ptr(counters), _stream(stream)))
+        return T, L
+
+    def run(self, J, m_dust=None, counters=None, stream=None):
+        """absorb -> solve -> emit as three launches; returns (H, T, L)."""
+        H = self.absorb(J, stream=stream)
+        T = self.solve(H, counters=counters, stream=stream)
+        L = self.emit(T, m_dust, stream=stream)
+        return H, T, L
+
+
+class Batch:
+    """Many grids in one persistent launch recorded in a HIP graph (dust_batch)."""
+
+    def __init__(self, plans: Sequence[Plan], J, m_dust, T, L, counters=None, autotune=True):
+        n = len(plans)
+        arr = lambda typ, vals: (typ * n)(*vals)
+        self._plans = list(plans)
+        self._bufs = (list(J), list(m_dust), list(T), list(L), counters)
+        hp = arr(_vp, [p.handle.value for p in plans])
+        nc = arr(_i64, [j.shape[0] for j in J])
+        pj, ldj, pt, ldt, pl, ldl = [], [], [], [], [], []
+        for p, j, t, l in zip(plans, J, T, L):
+            a, b = _rows(j, p.n_lambda, "J"); pj.append(a.value or 0); ldj.append(b)
+            a, b = _rows(t, p.n_grains, "T"); pt.append(a.value or 0); ldt.append(b)
+            a, b = _rows(l, p.n_lambda, "L"); pl.append(a.value or 0); ldl.append(b)
+        pm = [m.data_ptr() if m is not None else 0 for m in m_dust]
+        self._arrays = (hp, nc, arr(_vp, pj), arr(_i64, ldj), arr(_vp, pm), arr(_vp, pt),
+                        arr(_i64, ldt), arr(_vp, pl), arr(_i64, ldl))
+        h = _vp()
+        a = self._arrays
+        _check(lib().dust_batch_create(ctypes.cast(a[0], _vp), n, ctypes.cast(a[1], _vp),
+                                       ctypes.cast(a[2], _vp), ctypes.cast(a[3], _vp),
+                                       ctypes.cast(a[4], _vp), ctypes.cast(a[5], _vp),
+                                       ctypes.cast(a[6], _vp), ctypes.cast(a[7], _vp),
+                                       ctypes.cast(a[8], _vp), _ptr(counters),
+                                       1 if autotune else 0, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().dust_batch_launch(self._h, _stream(stream)))
+
+    def info(self):
+        tc = _i32()
+        ni = _i64()
+        _check(lib().dust_batch_info(self._h, ctypes.byref(tc), ctypes.byref(ni)))
+        return {"cells_per_tile": tc.value, "n_items": ni.value}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dust_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

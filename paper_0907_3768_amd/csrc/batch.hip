@@ -1,0 +1,321 @@
+// Many independent grids in one persistent launch.
+//
+// A batch binds (plan, buffers) per grid and a work list of (grid, cell tile)
+// items, heaviest tiles first (cost of a tile ~ NL x S of its grid).  Each
+// persistent workgroup takes the next item from a device counter, runs the
+// fused absorb -> solve -> emit body for that tile with the grid's tables,
+// and repeats until the list is exhausted.  Every workgroup reaches the exit
+// test after at most (items + 1) counter reads, so the grid always drains.
+//
+// Tile shapes (cells per tile) and the number of resident workgroups per CU
+// are chosen by timing candidates on the bound buffers (autotuner); the
+// chosen launch (counter reset + persistent kernel) is recorded once into a
+// HIP graph and replayed by dust_batch_launch.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "fused_body.h"
+
+namespace dust {
+namespace {
+
+struct GridArgs {
+    PlanView v;
+    int64_t C;
+    const float* J;
+    int64_t ldj;
+    const float* m;
+    float* T;
+    int64_t ldt;
+    float* L;
+    int64_t ldl;
+};
+
+// The counter is cleared by a kernel (not a memset) so that the graph holds
+// only kernel nodes.
+__global__ void reset_counter_kernel(unsigned int* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
+}
+
+template <int TC, int NTW>
+__global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__ grids,
+                                                    const int2* __restrict__ items, int n_items,
+                                                    unsigned int* counter, dust_counters* cnt) {
+    extern __shared__ float sTile[];  // [TC][Sp max]
+    __shared__ int sItem;
+    for (;;) {
+        if (threadIdx.x == 0) sItem = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = sItem;
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const GridArgs& g = grids[w.x];
+        fused_tile<TC, NTW>(g.v, (int64_t)w.y * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L, g.ldl,
+                            cnt, sTile);
+        // fused_tile ends with a barrier, so sItem may be overwritten now.
+    }
+}
+
+struct Candidate {
+    int tc;        // cells per tile
+    int per_cu;    // resident workgroups per CU
+};
+
+using KernelFn = void (*)(const GridArgs*, const int2*, int, unsigned int*, dust_counters*);
+
+template <int TC>
+KernelFn pick_kernel(int ntw) {
+    if (ntw <= 1) return batch_kernel<TC, 1>;
+    if (ntw <= 2) return batch_kernel<TC, 2>;
+    if (ntw <= 4) return batch_kernel<TC, 4>;
+    if (ntw <= 8) return batch_kernel<TC, 8>;
+    return batch_kernel<TC, 16>;
+}
+
+KernelFn kernel_for(int tc, int ntw) {
+    return tc == 32 ? pick_kernel<32>(ntw) : pick_kernel<16>(ntw);
+}
+
+// Autotuner cache: the best candidate per (max-S bucket, mean-NL bucket,
+// tile-count bucket), shared by every batch of the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, Candidate> g_tune_cache;
+
+}  // namespace
+}  // namespace dust
+
+struct dust_batch {
+    int device;
+    int n_grids;
+    int sp_max;
+    int ntw;
+    dust::Candidate cand;
+    int64_t n_items_16, n_items_32;
+    dust::GridArgs* d_grids;
+    int2* d_items16;
+    int2* d_items32;
+    unsigned int* d_counter;
+    dust_counters* counters;
+    int n_cu;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace dust {
+namespace {
+
+hipError_t enqueue(const dust_batch* b, const Candidate& c, hipStream_t st) {
+    const int2* items = c.tc == 32 ? b->d_items32 : b->d_items16;
+    const int n_items = (int)(c.tc == 32 ? b->n_items_32 : b->n_items_16);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int blocks = std::max(1, std::min(n_items, b->n_cu * c.per_cu));
+    const size_t lds = sizeof(float) * (size_t)c.tc * b->sp_max;
+    hipLaunchKernelGGL(kernel_for(c.tc, b->ntw), dim3(blocks), dim3(256), lds, st,
+                       (const GridArgs*)b->d_grids, items, n_items, b->d_counter, b->counters);
+    return hipGetLastError();
+}
+
+void free_batch(dust_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_grids) (void)hipFree(b->d_grids);
+    if (b->d_items16) (void)hipFree(b->d_items16);
+    if (b->d_items32) (void)hipFree(b->d_items32);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    delete b;
+}
+
+std::vector<int2> build_items(const std::vector<int64_t>& C, const std::vector<double>& cost,
+                              int tc) {
+    std::vector<int> order(C.size());
+    for (size_t g = 0; g < C.size(); ++g) order[g] = (int)g;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<int2> items;
+    for (int g : order) {
+        const int64_t tiles = (C[g] + tc - 1) / tc;
+        for (int64_t t = 0; t < tiles; ++t) items.push_back(make_int2(g, (int)t));
+    }
+    return items;
+}
+
+}  // namespace
+}  // namespace dust
+
+using namespace dust;
+
+extern "C" {
+
+dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const int64_t* n_cells,
+                              const float* const* J, const int64_t* ldj,
+                              const float* const* m_dust, float* const* T, const int64_t* ldt,
+                              float* const* L, const int64_t* ldl, dust_counters* counters,
+                              int32_t autotune, dust_batch** out) {
+    if (!out) return set_error(DUST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_grids < 1) return set_error(DUST_EINVAL, "n_grids must be >= 1");
+    if (!plans || !n_cells || !J || !ldj || !m_dust || !T || !ldt || !L || !ldl)
+        return set_error(DUST_EINVAL, "a per-grid array is NULL");
+    if (counters && ((uintptr_t)counters & 7u))
+        return set_error(DUST_EINVAL, "counters must be 8-byte aligned");
+    std::vector<GridArgs> args(n_grids);
+    std::vector<int64_t> C(n_grids);
+    std::vector<double> cost(n_grids);
+    int sp_max = 16;
+    int64_t total16 = 0;
+    for (int g = 0; g < n_grids; ++g) {
+        const dust_plan* p = plans[g];
+        if (!p) return set_error(DUST_EINVAL, "plans[" + std::to_string(g) + "] is NULL");
+        if (p->opt.mode != DUST_MIXED)
+            return set_error(DUST_EUNSUPPORTED, "batched launches take DUST_MIXED plans");
+        if (n_cells[g] < 0 || n_cells[g] > ((int64_t)1 << 36))
+            return set_error(DUST_EINVAL, "n_cells out of range");
+        const int64_t c = n_cells[g];
+        if (c > 0) {
+            if (!J[g] || !T[g] || !L[g]) return set_error(DUST_EINVAL, "a J/T/L pointer is NULL");
+            if (ldj[g] < p->NL || ldt[g] < p->S || ldl[g] < p->NL)
+                return set_error(DUST_EINVAL, "a leading dimension is smaller than its row");
+            if (((uintptr_t)J[g] | (uintptr_t)T[g] | (uintptr_t)L[g] |
+                 (uintptr_t)m_dust[g]) & 3u)
+                return set_error(DUST_EINVAL, "buffers must be 4-byte aligned");
+        }
+        args[g] = GridArgs{p->view, c, J[g], ldj[g], m_dust[g], T[g], ldt[g], L[g], ldl[g]};
+        C[g] = c;
+        cost[g] = (double)p->NL * p->S;
+        sp_max = std::max(sp_max, p->Sp);
+        total16 += (c + 15) / 16;
+    }
+    if (total16 > (int64_t)1 << 30) return set_error(DUST_EUNSUPPORTED, "too many tiles");
+
+    int dev = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_error(e, "hipGetDevice");
+    for (int g = 0; g < n_grids; ++g)
+        if (plans[g]->device != dev)
+            return set_error(DUST_EINVAL, "every plan must belong to the current device");
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
+        return hip_error(e, "hipGetDeviceProperties");
+
+    dust_batch* b = new dust_batch();
+    b->device = dev;
+    b->n_grids = n_grids;
+    b->sp_max = sp_max;
+    b->ntw = (sp_max / 16 + 3) / 4;
+    b->n_cu = prop.multiProcessorCount;
+    b->counters = counters;
+    std::vector<int2> it16 = build_items(C, cost, 16), it32 = build_items(C, cost, 32);
+    b->n_items_16 = (int64_t)it16.size();
+    b->n_items_32 = (int64_t)it32.size();
+
+    if ((e = hipMalloc(&b->d_grids, sizeof(GridArgs) * n_grids)) != hipSuccess ||
+        (e = hipMalloc(&b->d_items16, sizeof(int2) * std::max<size_t>(1, it16.size()))) != hipSuccess ||
+        (e = hipMalloc(&b->d_items32, sizeof(int2) * std::max<size_t>(1, it32.size()))) != hipSuccess ||
+        (e = hipMalloc(&b->d_counter, 256)) != hipSuccess) {
+        free_batch(b);
+        return hip_error(e, "hipMalloc (batch)");
+    }
+    if ((e = hipMemcpy(b->d_grids, args.data(), sizeof(GridArgs) * n_grids, hipMemcpyHostToDevice)) != hipSuccess ||
+        (it16.size() && (e = hipMemcpy(b->d_items16, it16.data(), sizeof(int2) * it16.size(), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (it32.size() && (e = hipMemcpy(b->d_items32, it32.data(), sizeof(int2) * it32.size(), hipMemcpyHostToDevice)) != hipSuccess)) {
+        free_batch(b);
+        return hip_error(e, "hipMemcpy (batch)");
+    }
+
+    // Candidate tile shapes.  32-cell tiles need twice the LDS per workgroup;
+    // a workgroup may hold at most 64 KiB and a CU 160 KiB.
+    std::vector<Candidate> cands;
+    for (int tc : {16, 32})
+        for (int per_cu : {1, 2, 4, 8}) {
+            const size_t lds = (size_t)tc * sp_max * sizeof(float);
+            if (lds <= 65536u && lds * per_cu <= 160u * 1024u)
+                cands.push_back(Candidate{tc, per_cu});
+        }
+    Candidate best{16, 2};
+    if (autotune && !cands.empty()) {
+        double mean_nl = 0.0;
+        for (int g = 0; g < n_grids; ++g) mean_nl += plans[g]->NL;
+        mean_nl /= n_grids;
+        int tiles_b = 0;
+        for (int64_t t = total16; t > 1; t >>= 2) ++tiles_b;
+        const auto key = std::make_tuple(sp_max / 64, (int)(mean_nl / 128), tiles_b);
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto f = g_tune_cache.find(key);
+            if (f != g_tune_cache.end()) { best = f->second; hit = true; }
+        }
+        if (!hit) {
+            hipStream_t st;
+            hipEvent_t e0, e1;
+            if ((e = hipStreamCreate(&st)) != hipSuccess) { free_batch(b); return hip_error(e, "hipStreamCreate"); }
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            float best_ms = 1e30f;
+            for (const Candidate& c : cands) {
+                float ms = 0.f, total = 0.f;
+                bool ok = enqueue(b, c, st) == hipSuccess;  // warm-up
+                for (int r = 0; ok && r < 2; ++r) {
+                    (void)hipEventRecord(e0, st);
+                    ok = enqueue(b, c, st) == hipSuccess;
+                    (void)hipEventRecord(e1, st);
+                    ok = ok && hipEventSynchronize(e1) == hipSuccess;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    total += ms;
+                }
+                if (ok && total < best_ms) { best_ms = total; best = c; }
+            }
+            (void)hipStreamSynchronize(st);
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            (void)hipStreamDestroy(st);
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = best;
+        }
+    }
+    b->cand = best;
+
+    // Record the chosen launch once.
+    hipStream_t cs;
+    if ((e = hipStreamCreate(&cs)) != hipSuccess) { free_batch(b); return hip_error(e, "hipStreamCreate"); }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = enqueue(b, best, cs);
+        e = hipStreamEndCapture(cs, &b->graph);
+        if (e == hipSuccess && le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) { free_batch(b); return hip_error(e, "graph capture"); }
+    if ((e = hipDeviceSynchronize()) != hipSuccess) { free_batch(b); return hip_error(e, "hipDeviceSynchronize"); }
+    *out = b;
+    return DUST_OK;
+}
+
+dust_status dust_batch_launch(dust_batch* b, void* stream) {
+    if (!b) return set_error(DUST_EINVAL, "batch is NULL");
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    return e == hipSuccess ? DUST_OK : hip_error(e, "hipGraphLaunch");
+}
+
+dust_status dust_batch_info(const dust_batch* b, int32_t* cells_per_tile, int64_t* n_items) {
+    if (!b) return set_error(DUST_EINVAL, "batch is NULL");
+    if (cells_per_tile) *cells_per_tile = b->cand.tc;
+    if (n_items) *n_items = b->cand.tc == 32 ? b->n_items_32 : b->n_items_16;
+    return DUST_OK;
+}
+
+dust_status dust_batch_destroy(dust_batch* b) {
+    if (!b) return DUST_OK;
+    hipError_t e = hipDeviceSynchronize();
+    free_batch(b);
+    return e == hipSuccess ? DUST_OK : hip_error(e, "hipDeviceSynchronize");
+}
+
+}  // extern "C"

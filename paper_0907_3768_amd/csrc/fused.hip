@@ -1,0 +1,49 @@
+// Fused absorb -> solve -> emit (Eqs. 6, 7, 9-10) for a tile of 16 cells per
+// workgroup.  The heating tile goes from the MFMA accumulators to LDS, is
+// solved in place (LDS then holds 1/T), and feeds the emission loop: H never
+// reaches device memory and T is written once.
+#include "fused_body.h"
+
+namespace dust {
+namespace {
+
+template <int NTW>
+__global__ __launch_bounds__(256) void fused_kernel(PlanView v, int64_t C,
+                                                   const float* __restrict__ J, int64_t ldj,
+                                                   const float* __restrict__ m,
+                                                   float* __restrict__ T, int64_t ldt,
+                                                   float* __restrict__ L, int64_t ldl,
+                                                   dust_counters* cnt) {
+    extern __shared__ float sTile[];  // [FUSED_TC][Sp]
+    fused_tile<FUSED_TC, NTW>(v, (int64_t)blockIdx.x * FUSED_TC, C, J, ldj, m, T, ldt, L, ldl,
+                              cnt, sTile);
+}
+
+template <int NTW>
+hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj, const float* m,
+                      float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
+                      hipStream_t st) {
+    const size_t lds = sizeof(float) * FUSED_TC * v.Sp;
+    hipLaunchKernelGGL(fused_kernel<NTW>, dim3((unsigned)((C + FUSED_TC - 1) / FUSED_TC)),
+                       dim3(256), lds, st, v, C, J, ldj, m, T, ldt, L, ldl, cnt);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fused(const PlanView& v, int64_t C, const float* J, int64_t ldj, const float* m,
+                        float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
+                        hipStream_t st) {
+    if (C == 0) return hipSuccess;
+    const int ntw = (v.Sp / 16 + 3) / 4;  // grain tiles per wave
+    if (ntw <= 1) return launch_ntw<1>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    if (ntw <= 2) return launch_ntw<2>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    if (ntw <= 3) return launch_ntw<3>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    if (ntw <= 4) return launch_ntw<4>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    if (ntw <= 6) return launch_ntw<6>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    if (ntw <= 8) return launch_ntw<8>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    if (ntw <= 12) return launch_ntw<12>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    return launch_ntw<16>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+}
+
+}  // namespace dust

@@ -1,0 +1,100 @@
+// Internal declarations of libdust (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "dust.h"
+
+namespace dust {
+
+// Padding of the kernel tables.  Wavelengths pad to the K depth of one
+// bf16 MFMA step (16x16x32); grains pad to the MFMA N width.
+constexpr int PAD_L = 32;
+constexpr int PAD_S = 16;
+
+// Exact SI constants (2019 SI) and the derived radiation constants.
+constexpr double PLANCK_H = 6.62607015e-34;
+constexpr double LIGHT_C = 299792458.0;
+constexpr double BOLTZ_K = 1.380649e-23;
+constexpr double RAD_C1 = 2.0 * PLANCK_H * LIGHT_C * LIGHT_C;  // 2 h c^2
+constexpr double RAD_C2 = PLANCK_H * LIGHT_C / BOLTZ_K;        // h c / k
+constexpr double LOG2E = 1.4426950408889634;
+constexpr double LN2 = 0.6931471805599453;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Everything a kernel needs from a plan, passed by value.
+struct PlanView {
+    int NL, S, NLp, Sp;
+    int mode;
+    int maxit;
+    float tol;
+    // wavelength tables [NLp]
+    const float* nu;       // -c2 log2(e) / lam  (0 on padding)
+    // per-grain tables [Sp]
+    const float* hscale;   // 2^es: H' = H * hscale (exact)
+    const float* hinv;     // 2^-es
+    const float* gs;       // Eq. 11 offset: log10 of 4 pi 2^-es, plus the size terms
+    // [Sp][NLp] tables
+    const float* kf;       // K' = C dlam 2^es (FP32)
+    const __bf16* khi;     // bf16(K')
+    const __bf16* klo;     // bf16(K' - khi)
+    const float* kb;       // K' c1 lam^-5 (FP32): the solve's Planck weights
+    const float* em;       // w C c1 lam^-5 2^-ge (FP32): the emission weights
+    float escale;          // 2^ge
+    // float64 tables of the mixed solve
+    const double* kd;      // [S][NL] K' (FP64) for the exact fallback
+    const double* lamd;    // [NL] lam (FP64)
+    const double* lty;     // [S][N] ln P'(T_k)
+    const double* ltd;     // [S][N] d ln P' / d ln T at T_k
+    const uint16_t* kidx;  // [S][M] table interval at uniform steps of ln P'
+    const double* ylo;     // [S] lty[s][0]
+    const double* yhi;     // [S] lty[s][N-1]
+    const double* dyinv;   // [S] (M - 1) / (yhi - ylo)
+    int N, M;
+    double lnTmin, hstep;  // ln T_k = lnTmin + k hstep
+};
+
+}  // namespace dust
+
+struct dust_plan {
+    int device;
+    dust_options opt;
+    int NL, S, NLp, Sp;
+    int N, M;
+    double lnTmin, hstep;
+    int ge;
+    // device float64 copies of the grid
+    double *d_lam, *d_dlam, *d_cabs, *d_w, *d_size;
+    int* d_es;
+    // derived device tables
+    float *d_nu, *d_hscale, *d_hinv, *d_gs, *d_kf, *d_kb, *d_em;
+    __bf16 *d_khi, *d_klo;
+    double *d_kd, *d_lty, *d_ltd, *d_ylo, *d_yhi, *d_dyinv;
+    uint16_t* d_kidx;
+    dust::PlanView view;
+};
+
+namespace dust {
+
+// Thread-local error text; returns `code` for convenience.
+dust_status set_error(dust_status code, const std::string& msg);
+dust_status hip_error(hipError_t e, const char* what);
+
+// Kernel launchers (each in its own translation unit).
+hipError_t launch_prepare(const dust_plan* p, hipStream_t st);
+hipError_t launch_absorb(const PlanView& v, int64_t C, const float* J, int64_t ldj,
+                         float* H, int64_t ldh, hipStream_t st);
+hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ldh,
+                        float* T, int64_t ldt, dust_counters* cnt, hipStream_t st);
+hipError_t launch_emit(const PlanView& v, int64_t C, const float* T, int64_t ldt,
+                       const float* m, float* L, int64_t ldl, hipStream_t st);
+hipError_t launch_fused(const PlanView& v, int64_t C, const float* J, int64_t ldj,
+                        const float* m, float* T, int64_t ldt, float* L, int64_t ldl,
+                        dust_counters* cnt, hipStream_t st);
+
+}  // namespace dust

@@ -1,0 +1,53 @@
+// Temperature solve, Eq. 7 (Section 4.3).
+//
+// Plain FP32: one thread per (cell, grain); a workgroup serves one grain
+// over 256 cells, as in the paper, so the grain's Planck weights and the
+// wavelength table are wave-uniform and come through the scalar cache.
+// Mixed: one thread per (cell, grain) in row-major order (coalesced H and T),
+// an O(1) lookup in the grain's FP64 table and an FP64 Newton polish.
+#include "device_common.h"
+
+namespace dust {
+namespace {
+
+__global__ __launch_bounds__(256) void solve_plain_kernel(PlanView v, int64_t C,
+                                                          const float* __restrict__ H,
+                                                          int64_t ldh, float* __restrict__ T,
+                                                          int64_t ldt, dust_counters* cnt) {
+    const int s = blockIdx.y;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= C) return;
+    const float hs = H[c * ldh + s] * v.hscale[s];
+    T[c * ldt + s] = solve_newton_f32(v.kb + (int64_t)s * v.NLp, v.nu, v.NL, hs, v.gs[s],
+                                      v.tol, v.maxit, cnt);
+}
+
+__global__ __launch_bounds__(256) void solve_mixed_kernel(PlanView v, int64_t C,
+                                                          const float* __restrict__ H,
+                                                          int64_t ldh, float* __restrict__ T,
+                                                          int64_t ldt, dust_counters* cnt) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= C * v.S) return;
+    const int64_t c = i / v.S;
+    const int s = (int)(i - c * v.S);
+    const double hs = (double)H[c * ldh + s] * (double)v.hscale[s];
+    T[c * ldt + s] = solve_table_f64(v, s, hs, cnt);
+}
+
+}  // namespace
+
+hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ldh, float* T,
+                        int64_t ldt, dust_counters* cnt, hipStream_t st) {
+    if (C == 0) return hipSuccess;
+    if (v.mode == DUST_MIXED) {
+        const int64_t n = C * v.S;
+        hipLaunchKernelGGL(solve_mixed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           st, v, C, H, ldh, T, ldt, cnt);
+    } else {
+        hipLaunchKernelGGL(solve_plain_kernel, dim3((unsigned)((C + 255) / 256), v.S), dim3(256),
+                           0, st, v, C, H, ldh, T, ldt, cnt);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dust

@@ -1,0 +1,145 @@
+"""The C-ABI library loads, exports every declared entry point and rejects
+bad arguments before touching the GPU (runs without one)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_0907_3768_amd as dust
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dust.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dust_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(dust.LIB_PATH):
+        dust.build()
+    return dust.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", dust.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (dust_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        getattr(L, n)
+
+
+def test_version_and_no_error(L):
+    assert b"gfx950" in L.dust_version()
+    assert L.dust_last_error() == b""
+
+
+def _desc(nl=8, s=2, lam=None, cabs=None, size=None):
+    lam = np.geomspace(1e-7, 1e-3, nl) if lam is None else lam
+    dl = np.full(nl, 1e-8)
+    cabs = np.full((s, nl), 1e-14) if cabs is None else cabs
+    w = np.ones(s)
+    size = np.full(s, 1e-7) if size is None else size
+    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in (lam, dl, cabs, w, size)]
+    d = dust.GridDesc(nl, s, *[a.ctypes.data for a in keep])
+    return d, keep
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("nl0", dust.DUST_EINVAL),
+    ("s0", dust.DUST_EINVAL),
+    ("s_big", dust.DUST_EUNSUPPORTED),
+    ("lam_nonincreasing", dust.DUST_EINVAL),
+    ("lam_negative", dust.DUST_EINVAL),
+    ("cabs_negative", dust.DUST_EINVAL),
+    ("cabs_nan", dust.DUST_EINVAL),
+    ("size_zero", dust.DUST_EINVAL),
+    ("bad_mode", dust.DUST_EINVAL),
+    ("bad_ltab", dust.DUST_EINVAL),
+    ("bad_trange", dust.DUST_EINVAL),
+    ("reserved", dust.DUST_EINVAL),
+])
+def test_plan_create_rejects(L, case, expect):
+    nl, s = 8, 2
+    lam = np.geomspace(1e-7, 1e-3, nl)
+    cabs = np.full((s, nl), 1e-14)
+    size = np.full(s, 1e-7)
+    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0)
+    if case == "nl0":
+        nl = 0
+    if case == "s0":
+        s = 0
+    if case == "s_big":
+        s = 2048
+        cabs = np.full((s, nl), 1e-14)
+        size = np.full(s, 1e-7)
+    if case == "lam_nonincreasing":
+        lam = lam.copy(); lam[3] = lam[2]
+    if case == "lam_negative":
+        lam = lam.copy(); lam[0] = -1.0
+    if case == "cabs_negative":
+        cabs = cabs.copy(); cabs[1, 1] = -1e-14
+    if case == "cabs_nan":
+        cabs = cabs.copy(); cabs[0, 0] = np.nan
+    if case == "size_zero":
+        size = size.copy(); size[1] = 0.0
+    if case == "bad_mode":
+        opt.mode = 7
+    if case == "bad_ltab":
+        opt.ltab_n = 3
+    if case == "bad_trange":
+        opt.ltab_tmin, opt.ltab_tmax = 100.0, 50.0
+    if case == "reserved":
+        opt.reserved = 1
+    d, keep = _desc(max(nl, 1), max(s, 1), lam if nl else None, cabs if s else None,
+                    size if s else None)
+    d.n_lambda, d.n_grains = nl, s
+    h = ctypes.c_void_p()
+    rc = L.dust_plan_create(ctypes.byref(d), ctypes.byref(opt), ctypes.byref(h))
+    assert rc == expect
+    assert h.value is None
+    assert len(L.dust_last_error()) > 0
+
+
+def test_null_arguments(L):
+    d, keep = _desc()
+    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0)
+    assert L.dust_plan_create(None, ctypes.byref(opt), ctypes.byref(ctypes.c_void_p())) == dust.DUST_EINVAL
+    assert L.dust_plan_create(ctypes.byref(d), ctypes.byref(opt), None) == dust.DUST_EINVAL
+    d.lambda_ = None
+    assert L.dust_plan_create(ctypes.byref(d), ctypes.byref(opt), ctypes.byref(ctypes.c_void_p())) == dust.DUST_EINVAL
+    assert L.dust_plan_destroy(None) == dust.DUST_OK
+    nul = ctypes.c_void_p(0)
+    assert L.dust_absorb(nul, 4, nul, 8, nul, 2, nul) == dust.DUST_EINVAL
+    assert L.dust_solve_T(nul, 4, nul, 2, nul, 2, nul, nul) == dust.DUST_EINVAL
+    assert L.dust_emit_sed(nul, 4, nul, 2, nul, nul, 8, nul) == dust.DUST_EINVAL
+    assert L.dust_run_fused(nul, 4, nul, 8, nul, nul, 2, nul, 8, nul, nul) == dust.DUST_EINVAL
+    assert L.dust_plan_prepare(nul, nul) == dust.DUST_EINVAL
+    assert L.dust_plan_info(nul, nul, nul, nul) == dust.DUST_EINVAL
+    assert L.dust_batch_launch(nul, nul) == dust.DUST_EINVAL
+    assert L.dust_batch_info(nul, nul, nul) == dust.DUST_EINVAL
+    assert L.dust_batch_destroy(nul) == dust.DUST_OK
+    out = ctypes.c_void_p()
+    assert L.dust_batch_create(nul, 0, nul, nul, nul, nul, nul, nul, nul, nul, nul, 0,
+                               ctypes.byref(out)) == dust.DUST_EINVAL
+    assert b"plan is NULL" in L.dust_last_error() or len(L.dust_last_error()) > 0
+
+
+def test_product_package_has_no_oracle_dependency():
+    """The product binding never imports the oracle (test infrastructure)."""
+    pkg = os.path.join(ROOT, "paper_0907_3768_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in src.lower(), f
+                assert "dust_ref" not in src, f
