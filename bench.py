@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Benchmark: (cell,grain) temperatures/s including the SED on one MI355X.
+
+One step is one pass of the whole path over one batch of synthetic cells:
+re-derive the grid's tables (prep, and the FP64 power tables in mixed mode)
+then absorb -> solve -> emit for every cell.  Inputs (J, dust masses) are
+resident in device memory before the timed region starts.
+
+Both precision forms run on the same inputs:
+  mixed  (the headline `value`): dust_plan_prepare + dust_run_fused
+  plain  (FP32 throughout):      dust_plan_prepare + dust_absorb +
+                                 dust_solve_T + dust_emit_sed
+Each is checked against the FP64 oracle on a strided sample of cells
+(relative T error <= 1e-4 and SED error <= 1e-3 are required), and the
+oracle itself is timed on the host cores on a bounded sample.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "(cell,grain) temperatures/s incl. SED; mixed vs plain FP32 at rel T err ≤1e-4"
+UNIT = "(cell,grain) temperatures/s"
+
+# MI355X (gfx950) unit counts and clock.
+N_CU = 256
+SIMD_PER_CU = 4
+LANES_PER_SIMD = 16
+CLOCK_HZ = 2.4e9
+HBM_PEAK_GBS = 8000.0
+# A wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles at full rate;
+# the transcendental instructions (v_exp_f32, v_rcp_f32) issue at a quarter
+# of that rate.  Every Planck term of Eq. 7 / Eq. 10 needs one exponential and
+# one reciprocal, so the transcendental peak bounds the Planck-term rate.
+TRANS_OPS_PER_S = N_CU * SIMD_PER_CU * LANES_PER_SIMD / 4.0 * CLOCK_HZ  # 9.83e12
+TERM_PEAK_PER_S = TRANS_OPS_PER_S / 2.0                                   # 4.92e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_0907_3768_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+FUSED_SOURCES = ["fused.hip", "fused_body.h", "device_common.h", "internal.h"]
+
+
+def measured_traffic(kernel_key, src_hash):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel_key)
+    if not e or e.get("source_hash") != src_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+class Timer:
+    """HIP events (torch's, on the current stream, where the kernels run) per stage."""
+
+    def __init__(self, torch, names):
+        self.torch = torch
+        self.ev = {n: [] for n in names}
+
+    def run(self, name, fn):
+        s = self.torch.cuda.Event(enable_timing=True)
+        e = self.torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        self.ev[name].append((s, e))
+
+    def mean_ms(self):
+        return {n: float(np.mean([s.elapsed_time(e) for s, e in v])) for n, v in self.ev.items() if v}
+
+
+def time_steps(torch, stages, steps, warmup):
+    for _ in range(warmup):
+        for _, fn in stages:
+            fn()
+    torch.cuda.synchronize()
+    timer = Timer(torch, [n for n, _ in stages])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for n, fn in stages:
+            timer.run(n, fn)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    return wall_ms, timer.mean_ms()
+
+
+def check_sample(grid, J, m_host, T, L, n_sample=64):
+    """Errors of (T, L) against the oracle on strided cells."""
+    import oracle
+    from oracle.compare import sed_errors, t_errors
+    C = J.shape[0]
+    rows = np.arange(min(n_sample, C)) * max(1, C // n_sample)
+    import torch
+    idx = torch.as_tensor(rows, device=J.device)
+    Jh = J[idx].cpu().numpy().astype(np.float64)
+    H_ref, T_ref, L_ref = oracle.run(grid, Jh, m_host[rows])
+    te = t_errors(T[idx].cpu().numpy(), T_ref, H_ref)
+    se = sed_errors(L[idx].cpu().numpy(), L_ref, grid.dlam)
+    return {"cells": int(len(rows)), "T_max_rel": te["max"], "T_p999_rel": te["p999"],
+            "SED_max_rel": se["max"], "SED_energy_l1": se["energy_l1"],
+            "SED_weighted_ratio_dev": se["weighted_ratio_dev"]}
+
+
+def cpu_baseline(grid, J, m_host, target_s):
+    """The oracle as it stands, on the host cores, on a strided sample of cells."""
+    import oracle
+    import torch
+    C = J.shape[0]
+    S = grid.n_grains
+
+    def run(n):
+        rows = np.arange(n) * max(1, C // n)
+        Jh = J[torch.as_tensor(rows, device=J.device)].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.run(grid, Jh, m_host[rows])
+        return time.perf_counter() - t0
+
+    n = min(256, C)
+    dt = run(n)
+    n2 = int(min(C, max(n, n * target_s / max(dt, 1e-3))))
+    if n2 > n:
+        n, dt = n2, run(n2)
+    return {"value": n * S / dt, "unit": UNIT, "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n} strided cells of the workload ({n * S} pairs, FP64 oracle incl. SED), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain-262144x250x80")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(cells are independent: each GPU would run its own share of cells with the "
+              "same kernels).", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    import paper_0907_3768_amd as dust
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS[args.workload]
+    grid = w.grid()
+    params = w.cells()
+    C, NL, S = w.n_cells, grid.n_lambda, grid.n_grains
+    log(f"workload {w.name}: C={C} NL={NL} S={S}; generating J on the device")
+    J = synth.radiation_field(params, grid.lam, device=dev)
+    m = torch.as_tensor(params.m_dust, dtype=torch.float32, device=dev)
+    T = torch.empty((C, S), dtype=torch.float32, device=dev)
+    L = torch.empty((C, NL), dtype=torch.float32, device=dev)
+    H = torch.empty((C, S), dtype=torch.float32, device=dev)
+    cnt = dust.new_counters(dev)
+    torch.cuda.synchronize()
+
+    pm = dust.Plan(grid, "mixed")
+    pp = dust.Plan(grid, "plain")
+
+    mixed_stages = [("prepare", lambda: pm.prepare()),
+                    ("fused", lambda: pm.fused(J, m, T, L, counters=cnt))]
+    plain_stages = [("prepare", lambda: pp.prepare()),
+                    ("absorb", lambda: pp.absorb(J, H)),
+                    ("solve", lambda: pp.solve(H, T, counters=cnt)),
+                    ("emit", lambda: pp.emit(T, m, L))]
+
+    log("timing mixed path")
+    mixed_ms, mixed_k = time_steps(torch, mixed_stages, args.steps, args.warmup)
+    cnt.zero_()
+    pm.fused(J, m, T, L, counters=cnt)
+    torch.cuda.synchronize()
+    mixed_cnt = cnt.cpu().tolist()
+    mixed_err = check_sample(grid, J, params.m_dust, T, L)
+
+    log("timing plain FP32 path")
+    plain_ms, plain_k = time_steps(torch, plain_stages, args.steps, args.warmup)
+    cnt.zero_()
+    pp.run(J, m, counters=cnt)
+    torch.cuda.synchronize()
+    plain_cnt = cnt.cpu().tolist()
+    plain_err = check_sample(grid, J, params.m_dust, T, L)
+
+    pairs = C * S
+    terms = C * S * NL
+    value = pairs / (mixed_ms * 1e-3)
+    plain_value = pairs / (plain_ms * 1e-3)
+
+    # Roofline of the dominant kernel (the fused absorb -> solve -> emit kernel):
+    # its algorithmic work is C*NL*S Planck terms of Eq. 10, bound by the
+    # transcendental issue rate (2 ops per term).
+    fused_ms = mixed_k["fused"]
+    achieved = terms / (fused_ms * 1e-3) / 1e9
+    peak = TERM_PEAK_PER_S / 1e9
+    src = source_hash(FUSED_SOURCES)
+    traffic = measured_traffic("fused_mixed:" + w.name, src)
+    alg_bytes = 4.0 * (C * NL + C * S + C * NL + C)  # J read, T write, L write, m read
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gterm/s",
+            "frac": achieved / peak, "traffic": traffic,
+            "kernel": "fused_kernel (absorb->solve->emit, mixed)",
+            "algorithmic_bytes": alg_bytes,
+            "hbm_GBps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9,
+            "hbm_frac_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "source_hash": src}
+
+    plain_solve_terms = None
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cells": C, "n_lambda": NL, "n_grains": S,
+                   "species": w.n_species, "sizes_per_species": w.n_sizes, "seed": w.seed,
+                   "path": "mixed: prepare + fused absorb->solve->emit",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "sed_cells_per_s": C / (mixed_ms * 1e-3),
+        "stages_ms": mixed_k,
+        "errors": mixed_err,
+        "counters": dict(zip(["nonfinite", "unconverged", "out_of_table"], mixed_cnt)),
+        "plain_fp32": {"value": plain_value, "ms_per_step": plain_ms, "stages_ms": plain_k,
+                       "sed_cells_per_s": C / (plain_ms * 1e-3), "errors": plain_err,
+                       "counters": dict(zip(["nonfinite", "unconverged", "out_of_table"], plain_cnt)),
+                       "dtype": "f32",
+                       "emit_Gterm_per_s": terms / (plain_k["emit"] * 1e-3) / 1e9},
+        "mixed_over_plain": value / plain_value,
+        "context_paper_c1060_temps_per_s": 1.52e6,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(grid, J, params.m_dust, args.cpu_seconds)
+    ok = (mixed_err["T_max_rel"] <= 1e-4 and plain_err["T_max_rel"] <= 1e-4 and
+          mixed_err["SED_max_rel"] <= 1e-3 and plain_err["SED_max_rel"] <= 1e-3)
+    out["accuracy_ok"] = bool(ok)
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 3
+
+
+if __name__ == "__main__":
+    sys.exit(main())
