@@ -40,11 +40,12 @@ LANES_PER_SIMD = 16
 CLOCK_HZ = 2.4e9
 HBM_PEAK_GBS = 8000.0
 # A wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles at full rate;
-# the transcendental instructions (v_exp_f32, v_rcp_f32) issue at a quarter
-# of that rate.  Every Planck term of Eq. 7 / Eq. 10 needs one exponential and
-# one reciprocal, so the transcendental peak bounds the Planck-term rate.
-TRANS_OPS_PER_S = N_CU * SIMD_PER_CU * LANES_PER_SIMD / 4.0 * CLOCK_HZ  # 9.83e12
-TERM_PEAK_PER_S = TRANS_OPS_PER_S / 2.0                                   # 4.92e12
+# on gfx950 the transcendental instructions (v_exp_f32, v_rcp_f32) issue at
+# half that rate (8 cycles per wave64 instruction).  A Planck term of Eq. 7 /
+# Eq. 10 needs one exponential and one reciprocal, so the transcendental unit
+# bounds the rate of Planck terms at half its op rate.
+TRANS_OPS_PER_S = N_CU * SIMD_PER_CU * LANES_PER_SIMD / 2.0 * CLOCK_HZ  # 1.97e13
+TERM_PEAK_PER_S = TRANS_OPS_PER_S / 2.0                                   # 9.83e12
 
 
 def log(*a):
@@ -209,6 +210,13 @@ def main():
     mixed_cnt = cnt.cpu().tolist()
     mixed_err = check_sample(grid, J, params.m_dust, T, L)
 
+    log("timing mixed path as three launches")
+    sep_stages = [("prepare", lambda: pm.prepare()),
+                  ("absorb", lambda: pm.absorb(J, H)),
+                  ("solve", lambda: pm.solve(H, T, counters=cnt)),
+                  ("emit", lambda: pm.emit(T, m, L))]
+    sep_ms, sep_k = time_steps(torch, sep_stages, args.steps, args.warmup)
+
     log("timing plain FP32 path")
     plain_ms, plain_k = time_steps(torch, plain_stages, args.steps, args.warmup)
     cnt.zero_()
@@ -267,6 +275,8 @@ def main():
                        "counters": dict(zip(["nonfinite", "unconverged", "out_of_table"], plain_cnt)),
                        "dtype": "f32",
                        "emit_Gterm_per_s": terms / (plain_k["emit"] * 1e-3) / 1e9},
+        "mixed_three_launches": {"ms_per_step": sep_ms, "stages_ms": sep_k,
+                                 "value": pairs / (sep_ms * 1e-3)},
         "mixed_over_plain": value / plain_value,
         "context_paper_c1060_temps_per_s": 1.52e6,
     }

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "device_common.h"
 
 namespace dust {
 
@@ -95,8 +95,8 @@ void free_plan(dust_plan* p) {
     if (!p) return;
     void* ptrs[] = {p->d_lam, p->d_dlam, p->d_cabs, p->d_w,   p->d_size, p->d_es,   p->d_nu,
                     p->d_hscale, p->d_hinv, p->d_gs, p->d_kf,  p->d_kb,   p->d_em,   p->d_khi,
-                    p->d_klo, p->d_kd,   p->d_lty,  p->d_ltd, p->d_ylo, p->d_yhi,  p->d_dyinv,
-                    p->d_kidx};
+                    p->d_klo, p->d_kdb,  p->d_c2l,  p->d_fwd, p->d_inv, p->d_ylo,  p->d_yhi,
+                    p->d_dyinv};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -162,6 +162,12 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     hipError_t e;
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_error(e, "hipGetDevice");
+    int max_lds = 65536;
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (emit_lds_bytes(16, Sp) > (size_t)max_lds)
+        return set_error(DUST_EUNSUPPORTED,
+                         "n_grains too large for one emission tile in LDS on this device (limit " +
+                             std::to_string(max_lds / (16 * 5)) + ")");
 
     dust_plan* p = new dust_plan;
     memset(p, 0, sizeof *p);
@@ -170,7 +176,7 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     p->NL = NL; p->S = S; p->NLp = NLp; p->Sp = Sp;
     p->ge = ge;
     p->N = o.ltab_n;
-    p->M = 4 * o.ltab_n;
+    p->M = o.ltab_n;
     p->lnTmin = log(o.ltab_tmin);
     p->hstep = (log(o.ltab_tmax) - log(o.ltab_tmin)) / (p->N - 1);
     const bool mixed = o.mode == DUST_MIXED;
@@ -195,11 +201,11 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     ALLOC(p->d_em, (size_t)Sp * NLp);
     ALLOC(p->d_khi, (size_t)Sp * NLp);
     ALLOC(p->d_klo, (size_t)Sp * NLp);
-    ALLOC(p->d_kd, (size_t)S * NL);
+    ALLOC(p->d_kdb, (size_t)S * NL);
+    ALLOC(p->d_c2l, NL);
     if (mixed) {
-        ALLOC(p->d_lty, (size_t)S * p->N);
-        ALLOC(p->d_ltd, (size_t)S * p->N);
-        ALLOC(p->d_kidx, (size_t)S * p->M);
+        ALLOC(p->d_fwd, (size_t)S * p->N);
+        ALLOC(p->d_inv, (size_t)S * p->M);
         ALLOC(p->d_ylo, S);
         ALLOC(p->d_yhi, S);
         ALLOC(p->d_dyinv, S);
@@ -239,11 +245,10 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     v.kb = p->d_kb;
     v.em = p->d_em;
     v.escale = ldexpf(1.0f, ge);
-    v.kd = p->d_kd;
-    v.lamd = p->d_lam;
-    v.lty = p->d_lty;
-    v.ltd = p->d_ltd;
-    v.kidx = p->d_kidx;
+    v.kdb = p->d_kdb;
+    v.c2l = p->d_c2l;
+    v.fwd = p->d_fwd;
+    v.inv = p->d_inv;
     v.ylo = p->d_ylo;
     v.yhi = p->d_yhi;
     v.dyinv = p->d_dyinv;

@@ -44,7 +44,7 @@ template <int TC, int NTW>
 __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__ grids,
                                                     const int2* __restrict__ items, int n_items,
                                                     unsigned int* counter, dust_counters* cnt) {
-    extern __shared__ float sTile[];  // [TC][Sp max]
+    extern __shared__ float sTile[];  // emit_lds_bytes(TC, Sp max)
     __shared__ int sItem;
     for (;;) {
         if (threadIdx.x == 0) sItem = (int)atomicAdd(counter, 1u);
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__
         if (it >= n_items) break;
         const int2 w = items[it];
         const GridArgs& g = grids[w.x];
-        fused_tile<TC, NTW>(g.v, (int64_t)w.y * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L, g.ldl,
+        fused_tile<DUST_MIXED, TC, NTW>(g.v, (int64_t)w.y * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L, g.ldl,
                             cnt, sTile);
         // fused_tile ends with a barrier, so sItem may be overwritten now.
     }
@@ -114,7 +114,7 @@ hipError_t enqueue(const dust_batch* b, const Candidate& c, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int blocks = std::max(1, std::min(n_items, b->n_cu * c.per_cu));
-    const size_t lds = sizeof(float) * (size_t)c.tc * b->sp_max;
+    const size_t lds = emit_lds_bytes(c.tc, b->sp_max);
     hipLaunchKernelGGL(kernel_for(c.tc, b->ntw), dim3(blocks), dim3(256), lds, st,
                        (const GridArgs*)b->d_grids, items, n_items, b->d_counter, b->counters);
     return hipGetLastError();
@@ -228,13 +228,15 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
         return hip_error(e, "hipMemcpy (batch)");
     }
 
+    int max_lds = 65536;
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     // Candidate tile shapes.  32-cell tiles need twice the LDS per workgroup;
     // a workgroup may hold at most 64 KiB and a CU 160 KiB.
     std::vector<Candidate> cands;
     for (int tc : {16, 32})
         for (int per_cu : {1, 2, 4, 8}) {
-            const size_t lds = (size_t)tc * sp_max * sizeof(float);
-            if (lds <= 65536u && lds * per_cu <= 160u * 1024u)
+            const size_t lds = emit_lds_bytes(tc, sp_max);
+            if (lds <= (size_t)max_lds && lds * per_cu <= 160u * 1024u)
                 cands.push_back(Candidate{tc, per_cu});
         }
     Candidate best{16, 2};

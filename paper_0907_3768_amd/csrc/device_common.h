@@ -6,18 +6,6 @@
 namespace dust {
 
 // ---------------------------------------------------------------------------
-// Planck factor in FP32.  With a = nu_l / T = -h c / (k lam_l T) log2(e),
-// y = 2^a = exp(-h c / (k lam T)) and B(lam, T) = c1 lam^-5 y / (1 - y).
-// Written in y (not e^{+x}) so that the deep Wien tail underflows to 0
-// instead of producing inf * 0.  Costs one v_exp_f32 and one v_rcp_f32.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float planck_factor(float nu, float invT) {
-    const float y = __builtin_amdgcn_exp2f(nu * invT);
-    const float q = __builtin_amdgcn_rcpf(1.0f - y);
-    return y * q;
-}
-
-// ---------------------------------------------------------------------------
 // Eq. 11 initial guess (Section 4.3) in natural-log units of T, floored at
 // 5 K.  hs is the scaled heating H' = H 2^es; gs folds log10(4 pi 2^-es)
 // and the size terms alpha1 log a + alpha2 log^2 a.
@@ -111,29 +99,57 @@ __device__ __forceinline__ float solve_newton_f32(const float* __restrict__ kb,
 }
 
 // ---------------------------------------------------------------------------
-// Exact FP64 solve of Eq. 7 for one pair, used by the mixed path when T lies
-// outside the table: Newton on ln P = ln H in ln T with the bracket
-// [lnlo, lnhi].  Rare, so it evaluates the sum directly.
+// e^x - 1 in FP64 for x >= 0: exp(x) - 1 where that loses at most a few
+// units in the last place relative (x >= 0.01: <= 2.3e-14), the Taylor series
+// to x^7 below (truncation x^8/8! < 3e-21 relative).  Lighter on registers
+// than the library expm1.
 // ---------------------------------------------------------------------------
-__device__ inline double solve_exact_f64(const PlanView& v, int s, double hs,
-                                         double lnlo, double lnhi, bool* ok) {
-    const double* kd = v.kd + (int64_t)s * v.NL;
+__device__ __forceinline__ double expm1_pos(double x) {
+    if (x >= 0.01) return exp(x) - 1.0;
+    const double p = 1.0 + x * (1.0 / 2 + x * (1.0 / 6 + x * (1.0 / 24 + x * (1.0 / 120 +
+                     x * (1.0 / 720 + x * (1.0 / 5040))))));
+    return x * p;
+}
+
+// ---------------------------------------------------------------------------
+// Exact FP64 power of grain s at T and T dP/dT (Eq. 7's right side), summed
+// over wavelengths by the whole wave: lane i takes wavelengths i, i+64, ...;
+// a butterfly reduction leaves both totals in every lane.  Every lane of the
+// wave must call it with the same (s, T).
+// ---------------------------------------------------------------------------
+__device__ inline void wave_power_f64(const PlanView& v, int s, double T, double* P, double* D) {
+    const int lane = threadIdx.x & 63;
+    const double* kdb = v.kdb + (int64_t)s * v.NL;
+    const double invT = 1.0 / T;
+    double p = 0.0, d = 0.0;
+#pragma unroll 1
+    for (int l = lane; l < v.NL; l += 64) {
+        const double x = v.c2l[l] * invT;
+        const double r = 1.0 / expm1_pos(x);  // 0 once e^x overflows
+        const double b = kdb[l] * r;
+        p += b;
+        d += b * x * (1.0 + r);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        p += __shfl_xor(p, off, 64);
+        d += __shfl_xor(d, off, 64);
+    }
+    *P = p;
+    *D = d;
+}
+
+// Exact FP64 solve of Eq. 7 for one pair, by the whole wave (uniform
+// arguments): Newton on ln P = ln H in ln T from lnT0, safeguarded by the
+// bracket [lnlo, lnhi].  Used by the mixed path for pairs outside the table.
+__device__ inline double wave_solve_exact_f64(const PlanView& v, int s, double hs, double lnlo,
+                                              double lnhi, double lnT0, bool* ok) {
     const double lnH = log(hs);
     double lo = lnlo, hi = lnhi;
-    double lnT = 0.5 * (lo + hi);
-    for (int it = 0; it < 200; ++it) {
-        const double T = exp(lnT);
-        double P = 0.0, D = 0.0;
-        for (int l = 0; l < v.NL; ++l) {
-            const double lam = v.lamd[l];
-            const double x = RAD_C2 / (lam * T);
-            const double em1 = expm1(x);
-            if (__builtin_isinf(em1)) continue;
-            const double l2 = lam * lam;
-            const double b = RAD_C1 / (l2 * l2 * lam) / em1;
-            P += kd[l] * b;
-            D += kd[l] * b * x * ((em1 + 1.0) / em1);
-        }
+    double lnT = (lnT0 > lo && lnT0 < hi) ? lnT0 : 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        double P, D;
+        wave_power_f64(v, s, exp(lnT), &P, &D);
         double next;
         if (!(P > 0.0)) {
             lo = lnT;
@@ -153,73 +169,157 @@ __device__ inline double solve_exact_f64(const PlanView& v, int s, double hs,
 }
 
 // ---------------------------------------------------------------------------
-// Mixed solve of Eq. 7 for one pair from the FP64 table of y = ln P'(ln T):
-// locate the table interval through the uniform-in-y index, then Newton in
-// FP64 on the cubic Hermite interpolant of y(ln T) over that interval.
-// Out-of-table pairs fall back to the exact FP64 solve.  Returns T.
+// Mixed solve of Eq. 7 from the grain's FP64 tables.  y = ln H' is located in
+// the inverse table (uniform in y: no search), whose cubic Hermite gives a
+// starting ln T; the forward table interval that holds it then gives the
+// cubic Hermite interpolant p(theta) of y(ln T), on which FP64 Newton steps
+// polish ln T.  Each table read is one 32-byte pair of double2.
+// Returns 0 with *T set, or, for a pair the table does not cover, a pending
+// code with *lnT0 a starting point for the exact solve:
+//   1: below the table, 2: above it, 3: the grain's table is not finite.
 // ---------------------------------------------------------------------------
-__device__ inline float solve_table_f64(const PlanView& v, int s, double hs,
-                                        dust_counters* cnt) {
+__device__ __forceinline__ double hermite(double t, double y0, double m0, double y1, double m1,
+                                          double* dp) {
+    const double t2 = t * t, t3 = t2 * t;
+    *dp = (6.0 * t2 - 6.0 * t) * (y0 - y1) + (3.0 * t2 - 4.0 * t + 1.0) * m0 +
+          (3.0 * t2 - 2.0 * t) * m1;
+    return (2.0 * t3 - 3.0 * t2 + 1.0) * y0 + (t3 - 2.0 * t2 + t) * m0 +
+           (3.0 * t2 - 2.0 * t3) * y1 + (t3 - t2) * m1;
+}
+
+__device__ inline int table_lookup_f64(const PlanView& v, int s, double hs, float* T,
+                                       double* lnT0, dust_counters* cnt) {
     if (!(hs >= 0.0) || __builtin_isinf(hs)) {
         if (cnt) count(&cnt->n_nonfinite);
-        return __builtin_nanf("");
+        *T = __builtin_nanf("");
+        return 0;
     }
-    if (hs == 0.0) return 0.0f;
+    if (hs == 0.0) { *T = 0.0f; return 0; }
     const double y = log(hs);
     const double ylo = v.ylo[s], yhi = v.yhi[s];
-    const bool table_ok = __builtin_isfinite(ylo) && __builtin_isfinite(yhi);
-    if (!table_ok || !(y >= ylo && y <= yhi)) {
-        // Outside the table (or a grain whose power underflows at the table's
-        // low end): exact FP64 solve on the matching side of the range.
-        bool ok = false;
-        const double lnTmax = v.lnTmin + (v.N - 1) * v.hstep;
-        double lnT;
-        if (table_ok && y < ylo)
-            lnT = solve_exact_f64(v, s, hs, log(1e-3), v.lnTmin, &ok);
-        else if (table_ok)
-            lnT = solve_exact_f64(v, s, hs, lnTmax, log(1e7), &ok);
-        else
-            lnT = solve_exact_f64(v, s, hs, log(1e-3), log(1e7), &ok);
-        if (cnt) {
-            count(&cnt->n_out_of_table);
-            if (!ok) count(&cnt->n_unconverged);
-        }
-        return (float)exp(lnT);
-    }
     const int N = v.N, M = v.M;
-    int j = (int)((y - ylo) * v.dyinv[s]);
-    j = j < 0 ? 0 : (j > M - 1 ? M - 1 : j);
-    int k = v.kidx[(int64_t)s * M + j];
-    const double* ty = v.lty + (int64_t)s * N;
-    const double* td = v.ltd + (int64_t)s * N;
-    while (k < N - 2 && ty[k + 1] <= y) ++k;
-    while (k > 0 && ty[k] > y) --k;
-    const double y0 = ty[k], y1 = ty[k + 1];
-    const double m0 = td[k] * v.hstep, m1 = td[k + 1] * v.hstep;
-    double th = (y1 > y0) ? (y - y0) / (y1 - y0) : 0.0;
-    for (int it = 0; it < 3; ++it) {
-        const double t2 = th * th, t3 = t2 * th;
-        const double p = (2.0 * t3 - 3.0 * t2 + 1.0) * y0 + (t3 - 2.0 * t2 + th) * m0 +
-                         (3.0 * t2 - 2.0 * t3) * y1 + (t3 - t2) * m1;
-        const double dp = (6.0 * t2 - 6.0 * th) * y0 + (3.0 * t2 - 4.0 * th + 1.0) * m0 +
-                          (6.0 * th - 6.0 * t2) * y1 + (3.0 * t2 - 2.0 * th) * m1;
-        th -= (p - y) / dp;
-        th = th < 0.0 ? 0.0 : (th > 1.0 ? 1.0 : th);
+    const double2* f = v.fwd + (int64_t)s * N;
+    if (!(__builtin_isfinite(ylo) && __builtin_isfinite(yhi))) { *lnT0 = 0.0; return 3; }
+    if (y < ylo) {
+        *lnT0 = v.lnTmin + (y - ylo) * v.hstep / f[0].y;
+        return 1;
     }
-    return (float)exp(v.lnTmin + ((double)k + th) * v.hstep);
+    if (y > yhi) {
+        *lnT0 = v.lnTmin + (N - 1) * v.hstep + (y - yhi) * v.hstep / f[N - 1].y;
+        return 2;
+    }
+    // inverse table: ln T(y) at uniform nodes
+    const double uj = (y - ylo) * v.dyinv[s];
+    int j = (int)uj;
+    j = j < 0 ? 0 : (j > M - 2 ? M - 2 : j);
+    const double2* g = v.inv + (int64_t)s * M + j;
+    const double2 g0 = g[0], g1 = g[1];
+    double dummy;
+    const double lnT_start = hermite(uj - j, g0.x, g0.y, g1.x, g1.y, &dummy);
+    // forward interval holding the start, then Newton on its cubic
+    const double kt = (lnT_start - v.lnTmin) / v.hstep;
+    int k = (int)kt;
+    k = k < 0 ? 0 : (k > N - 2 ? N - 2 : k);
+    const double2 a = f[k], b = f[k + 1];
+    double th = kt - k;
+    for (int it = 0; it < 2; ++it) {
+        double dp;
+        const double p = hermite(th, a.x, a.y, b.x, b.y, &dp);
+        th -= (p - y) / dp;
+    }
+    *T = (float)exp(v.lnTmin + ((double)k + th) * v.hstep);
+    return 0;
+}
+
+// Mixed solve of one pair per lane.  Every lane of the wave must call it
+// (inactive lanes pass active = false); pairs outside the table are then
+// solved exactly one after another by the whole wave.
+__device__ inline float wave_solve_mixed(const PlanView& v, bool active, int s, double hs,
+                                         dust_counters* cnt) {
+    float T = 0.0f;
+    double lnT0 = 0.0;
+    const int status = active ? table_lookup_f64(v, s, hs, &T, &lnT0, cnt) : 0;
+    uint64_t pend = __ballot(status != 0);
+    const int lane = threadIdx.x & 63;
+    const double lnTmax = v.lnTmin + (v.N - 1) * v.hstep;
+    while (pend) {
+        const int src = __ffsll((unsigned long long)pend) - 1;
+        pend &= pend - 1;
+        const int ss = __shfl(s, src, 64);
+        const double hh = __shfl(hs, src, 64);
+        const int st = __shfl(status, src, 64);
+        const double g = __shfl(lnT0, src, 64);
+        const double lo = (st == 2) ? lnTmax : -6.907755278982137;  // ln 1e-3
+        const double hi = (st == 1) ? v.lnTmin : 16.11809565095832;  // ln 1e7
+        bool ok = false;
+        const double lnT = wave_solve_exact_f64(v, ss, hh, lo, hi, g, &ok);
+        if (lane == src) {
+            T = (float)exp(lnT);
+            if (cnt) {
+                count(&cnt->n_out_of_table);
+                if (!ok) count(&cnt->n_unconverged);
+            }
+        }
+    }
+    return T;
 }
 
 // ---------------------------------------------------------------------------
-// Emission of TC cells at one wavelength (Eqs. 9-10, Section 4.4): the lane
-// owns wavelength l and accumulates sum_s em[s,l] B-factor(nu_l / T[c,s])
-// for each of its TC cells.  sInvT is the tile's 1/T in LDS, [TC][Sp]
-// (wave-uniform addresses: broadcast reads).  em points at column l of the
-// emission-weight table (stride NLp).
+// Emission of TC cells at one wavelength (Eqs. 9-10, Section 4.4).
+//
+// The lane owns wavelength l and accumulates, for each of its TC cells,
+//   sum_s em[s,l] / (2^t - 1),   t = u_l / T[c,s],  u_l = h c log2(e) / (k lam_l)
+// (em already holds w_s C[s,l] c1 lam_l^-5).  nu = -u_l.
+//
+// LDS tile (filled by the caller):
+//   sInvT  [TC][Sp]  1/T per cell and grain (+inf for T = 0, NaN for bad T);
+//   sChunk [Sp/4][TC] bits of the smallest 1/T over each group of 4 grains
+//                     (0 when the group holds a NaN).
+// Both are read with wave-uniform addresses (LDS broadcast).
+//
+// For each (4-grain group, cell) the wave picks one evaluation, uniformly, by
+// comparing the group's hottest grain at the wave's longest wavelength
+// (smallest t over the wave's lanes) with three thresholds:
+//   t >= 150      every term is exactly 0 in FP32 (2^-150 underflows): skip;
+//   24 <= t       1/(2^t - 1) = y + O(y^2), y = 2^-t <= 2^-24: use y;
+//   12 <= t < 24  use y + y^2 (error y^3 <= 2^-36 relative);
+//   otherwise     the exact form rcp(2^t - 1).
+// The comparisons are on the float bit patterns of non-negative values (their
+// order is that of unsigned integers), so they run on the scalar unit.
+// Costs per term: 0, 2 VALU + 1 exp, 3 VALU + 1 exp, 3 VALU + exp + rcp.
 // ---------------------------------------------------------------------------
+// LDS bytes of an emission tile of TC cells: sInvT plus sChunk.
+__host__ __device__ constexpr size_t emit_lds_bytes(int TC, int Sp) {
+    return (size_t)TC * (size_t)Sp * sizeof(float) + (size_t)(Sp / 4) * TC * sizeof(uint32_t);
+}
+
+__device__ __forceinline__ uint32_t chunk_min_bits(float a, float b, float c, float d) {
+    if (__builtin_isnan(a) || __builtin_isnan(b) || __builtin_isnan(c) || __builtin_isnan(d))
+        return 0u;  // forces the exact form, which propagates the NaN
+    return __float_as_uint(fminf(fminf(a, b), fminf(c, d)));
+}
+
+// Fill sChunk from sInvT (all threads of the block; caller synchronises).
+template <int TC>
+__device__ __forceinline__ void fill_chunk_min(const float* sInvT, uint32_t* sChunk, int Sp) {
+    const int SC = Sp >> 2;
+    for (int i = threadIdx.x; i < TC * SC; i += blockDim.x) {
+        const int ch = i / TC, cc = i - ch * TC;
+        const float4 t = *reinterpret_cast<const float4*>(sInvT + cc * Sp + 4 * ch);
+        sChunk[i] = chunk_min_bits(t.x, t.y, t.z, t.w);
+    }
+}
+
 template <int TC>
 __device__ __forceinline__ void emit_accumulate(const float* __restrict__ em, int NLp,
-                                                float nu, const float* sInvT, int Sp,
-                                                int S, float (&acc)[TC]) {
+                                                float nu, float u_wave_min,
+                                                const float* sInvT, const uint32_t* sChunk,
+                                                int Sp, int S, float (&acc)[TC]) {
+    static_assert(TC % 4 == 0, "cells per tile must be a multiple of 4");
+    // Thresholds on 1/T for this wave (uniform).
+    const uint32_t thr_skip = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(150.0f / u_wave_min));
+    const uint32_t thr_y = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(24.0f / u_wave_min));
+    const uint32_t thr_y2 = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(12.0f / u_wave_min));
 #pragma unroll
     for (int cc = 0; cc < TC; ++cc) acc[cc] = 0.0f;
     for (int s = 0; s < S; s += 4) {
@@ -227,17 +327,55 @@ __device__ __forceinline__ void emit_accumulate(const float* __restrict__ em, in
         const float e1 = em[(int64_t)(s + 1) * NLp];
         const float e2 = em[(int64_t)(s + 2) * NLp];
         const float e3 = em[(int64_t)(s + 3) * NLp];
+        const uint32_t* cmrow = sChunk + (s >> 2) * TC;
 #pragma unroll
-        for (int cc = 0; cc < TC; ++cc) {
-            const float4 it = *reinterpret_cast<const float4*>(sInvT + cc * Sp + s);
-            float a = acc[cc];
-            a = fmaf(e0, planck_factor(nu, it.x), a);
-            a = fmaf(e1, planck_factor(nu, it.y), a);
-            a = fmaf(e2, planck_factor(nu, it.z), a);
-            a = fmaf(e3, planck_factor(nu, it.w), a);
-            acc[cc] = a;
+        for (int c4 = 0; c4 < TC; c4 += 4) {
+            const uint4 cm4 = *reinterpret_cast<const uint4*>(cmrow + c4);
+            const uint32_t cms[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(cm4.x),
+                                     (uint32_t)__builtin_amdgcn_readfirstlane(cm4.y),
+                                     (uint32_t)__builtin_amdgcn_readfirstlane(cm4.z),
+                                     (uint32_t)__builtin_amdgcn_readfirstlane(cm4.w)};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int cc = c4 + k;
+                const uint32_t cm = cms[k];
+                if (cm >= thr_skip) continue;
+                const float4 it = *reinterpret_cast<const float4*>(sInvT + cc * Sp + s);
+                float a = acc[cc];
+                if (cm >= thr_y) {
+                    a = fmaf(e0, __builtin_amdgcn_exp2f(nu * it.x), a);
+                    a = fmaf(e1, __builtin_amdgcn_exp2f(nu * it.y), a);
+                    a = fmaf(e2, __builtin_amdgcn_exp2f(nu * it.z), a);
+                    a = fmaf(e3, __builtin_amdgcn_exp2f(nu * it.w), a);
+                } else if (cm >= thr_y2) {
+                    float y;
+                    y = __builtin_amdgcn_exp2f(nu * it.x); a = fmaf(e0, fmaf(y, y, y), a);
+                    y = __builtin_amdgcn_exp2f(nu * it.y); a = fmaf(e1, fmaf(y, y, y), a);
+                    y = __builtin_amdgcn_exp2f(nu * it.z); a = fmaf(e2, fmaf(y, y, y), a);
+                    y = __builtin_amdgcn_exp2f(nu * it.w); a = fmaf(e3, fmaf(y, y, y), a);
+                } else {
+                    a = fmaf(e0, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it.x)) - 1.0f), a);
+                    a = fmaf(e1, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it.y)) - 1.0f), a);
+                    a = fmaf(e2, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it.z)) - 1.0f), a);
+                    a = fmaf(e3, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it.w)) - 1.0f), a);
+                }
+                acc[cc] = a;
+            }
         }
     }
+}
+
+// 1/T as the emission tile stores it: T < 0 or NaN gives NaN (the cell's SED
+// becomes NaN), T = 0 gives +inf (the grain emits nothing).
+__device__ __forceinline__ float inv_temperature(float t) {
+    return (t >= 0.0f) ? 1.0f / t : __builtin_nanf("");
+}
+
+// Smallest u = -nu over the valid wavelengths of the wave that owns
+// wavelengths [l_wave0, l_wave0 + 64): the one at its longest wavelength.
+__device__ __forceinline__ float wave_u_min(const float* nu, int l_wave0, int NL) {
+    const int lw = (l_wave0 + 63 < NL) ? l_wave0 + 63 : NL - 1;
+    return -nu[lw];
 }
 
 }  // namespace dust

@@ -18,19 +18,25 @@ __global__ __launch_bounds__(256) void emit_kernel(PlanView v, int64_t C,
                                                    const float* __restrict__ T, int64_t ldt,
                                                    const float* __restrict__ m,
                                                    float* __restrict__ L, int64_t ldl) {
-    extern __shared__ float sInvT[];  // [TC][Sp]
+    extern __shared__ float smem[];  // sInvT [TC][Sp], then sChunk [Sp/4][TC]
+    float* sInvT = smem;
+    uint32_t* sChunk = reinterpret_cast<uint32_t*>(smem + TC * v.Sp);
     const int64_t c0 = (int64_t)blockIdx.x * TC;
     for (int i = threadIdx.x; i < TC * v.Sp; i += 256) {
         const int cc = i / v.Sp, s = i - cc * v.Sp;
-        const float t = (c0 + cc < C && s < v.S) ? T[(c0 + cc) * ldt + s] : 0.0f;
-        sInvT[i] = 1.0f / t;  // T = 0 gives +inf: the grain emits nothing
+        sInvT[i] = (c0 + cc < C && s < v.S) ? inv_temperature(T[(c0 + cc) * ldt + s])
+                                             : __builtin_inff();
     }
     __syncthreads();
+    fill_chunk_min<TC>(sInvT, sChunk, v.Sp);
+    __syncthreads();
+    const int lw0 = blockIdx.y * 256 + (threadIdx.x & ~63);
     const int l = blockIdx.y * 256 + threadIdx.x;
     const bool lv = l < v.NL;
     const float nu = v.nu[lv ? l : 0];
     float acc[TC];
-    emit_accumulate<TC>(v.em + (lv ? l : 0), v.NLp, nu, sInvT, v.Sp, v.S, acc);
+    emit_accumulate<TC>(v.em + (lv ? l : 0), v.NLp, nu, wave_u_min(v.nu, lw0, v.NL), sInvT,
+                        sChunk, v.Sp, v.S, acc);
     if (!lv) return;
 #pragma unroll
     for (int cc = 0; cc < TC; ++cc) {
@@ -45,7 +51,7 @@ hipError_t launch_emit(const PlanView& v, int64_t C, const float* T, int64_t ldt
                        const float* m, float* L, int64_t ldl, hipStream_t st) {
     if (C == 0) return hipSuccess;
     dim3 grid((unsigned)((C + EMIT_TC - 1) / EMIT_TC), (unsigned)((v.NL + 255) / 256));
-    const size_t lds = sizeof(float) * EMIT_TC * v.Sp;
+    const size_t lds = emit_lds_bytes(EMIT_TC, v.Sp);
     hipLaunchKernelGGL(emit_kernel<EMIT_TC>, grid, dim3(256), lds, st, v, C, T, ldt, m, L, ldl);
     return hipGetLastError();
 }

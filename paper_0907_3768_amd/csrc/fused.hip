@@ -7,15 +7,15 @@
 namespace dust {
 namespace {
 
-template <int NTW>
+template <int MODE, int NTW>
 __global__ __launch_bounds__(256) void fused_kernel(PlanView v, int64_t C,
                                                    const float* __restrict__ J, int64_t ldj,
                                                    const float* __restrict__ m,
                                                    float* __restrict__ T, int64_t ldt,
                                                    float* __restrict__ L, int64_t ldl,
                                                    dust_counters* cnt) {
-    extern __shared__ float sTile[];  // [FUSED_TC][Sp]
-    fused_tile<FUSED_TC, NTW>(v, (int64_t)blockIdx.x * FUSED_TC, C, J, ldj, m, T, ldt, L, ldl,
+    extern __shared__ float sTile[];
+    fused_tile<MODE, FUSED_TC, NTW>(v, (int64_t)blockIdx.x * FUSED_TC, C, J, ldj, m, T, ldt, L, ldl,
                               cnt, sTile);
 }
 
@@ -23,9 +23,14 @@ template <int NTW>
 hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj, const float* m,
                       float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
                       hipStream_t st) {
-    const size_t lds = sizeof(float) * FUSED_TC * v.Sp;
-    hipLaunchKernelGGL(fused_kernel<NTW>, dim3((unsigned)((C + FUSED_TC - 1) / FUSED_TC)),
-                       dim3(256), lds, st, v, C, J, ldj, m, T, ldt, L, ldl, cnt);
+    const size_t lds = emit_lds_bytes(FUSED_TC, v.Sp);
+    const dim3 grid((unsigned)((C + FUSED_TC - 1) / FUSED_TC));
+    if (v.mode == DUST_MIXED)
+        hipLaunchKernelGGL((fused_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v, C, J, ldj,
+                           m, T, ldt, L, ldl, cnt);
+    else
+        hipLaunchKernelGGL((fused_kernel<DUST_PLAIN_FP32, NTW>), grid, dim3(256), lds, st, v, C, J,
+                           ldj, m, T, ldt, L, ldl, cnt);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ constexpr int FUSED_TC = 16;  // default cells per tile (one MFMA M-block)
 // Phase 1: heating of a 16-cell block into sH[16][Sp] (rows of the tile's
 // LDS array) in the plan's scaled units H' = H 2^es.  Wave w computes grain
 // tiles w, w+4, ... (NTW of them).
-template <int NTW>
+template <int MODE, int NTW>
 __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int64_t C,
                                              const float* __restrict__ J, int64_t ldj,
                                              float* sH) {
@@ -26,7 +26,7 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    if (v.mode == DUST_MIXED) {
+    if constexpr (MODE == DUST_MIXED) {
         for (int k0 = 0; k0 < v.NL; k0 += 32) {
             const int kb = k0 + kq * 8;
             float x[8];
@@ -83,30 +83,35 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
 }
 
 // Phases 2 and 3 on a tile whose scaled heating sits in sH: solve every pair
-// (T to device memory, 1/T back into sH), then emit the tile's SEDs.
-template <int TC>
+// (T to device memory, 1/T back into sH), then emit the tile's SEDs.  The
+// group minima of 1/T follow sH in LDS (see emit_accumulate).
+template <int MODE, int TC>
 __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, int64_t C,
                                                  const float* __restrict__ m,
                                                  float* __restrict__ T, int64_t ldt,
                                                  float* __restrict__ L, int64_t ldl,
                                                  dust_counters* cnt, float* sH) {
     const int n = TC * v.Sp;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    // Same trip count for every lane: the mixed solve works wave-wide.
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int i = base + threadIdx.x;
         const int cc = i / v.Sp, s = i - cc * v.Sp;
         const int64_t c = c0 + cc;
-        float inv = __builtin_inff();
-        if (s < v.S && c < C) {
-            float t;
-            if (v.mode == DUST_MIXED)
-                t = solve_table_f64(v, s, (double)sH[i], cnt);
-            else
+        const bool pair = i < n && s < v.S && c < C;
+        float t = 0.0f;
+        if constexpr (MODE == DUST_MIXED) {
+            t = wave_solve_mixed(v, pair, pair ? s : 0, pair ? (double)sH[i] : 0.0, cnt);
+        } else {
+            if (pair)
                 t = solve_newton_f32(v.kb + (int64_t)s * v.NLp, v.nu, v.NL, sH[i], v.gs[s],
                                      v.tol, v.maxit, cnt);
-            T[c * ldt + s] = t;
-            inv = 1.0f / t;
         }
-        sH[i] = inv;
+        if (pair) T[c * ldt + s] = t;
+        if (i < n) sH[i] = pair ? inv_temperature(t) : __builtin_inff();
     }
+    __syncthreads();
+    uint32_t* sChunk = reinterpret_cast<uint32_t*>(sH + n);
+    fill_chunk_min<TC>(sH, sChunk, v.Sp);
     __syncthreads();
     float mc[TC];
 #pragma unroll
@@ -118,8 +123,9 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
         const int l = l0 + threadIdx.x;
         const bool lv = l < v.NL;
         const float nu = v.nu[lv ? l : 0];
+        const float uw = wave_u_min(v.nu, l0 + (threadIdx.x & ~63), v.NL);
         float acc[TC];
-        emit_accumulate<TC>(v.em + (lv ? l : 0), v.NLp, nu, sH, v.Sp, v.S, acc);
+        emit_accumulate<TC>(v.em + (lv ? l : 0), v.NLp, nu, uw, sH, sChunk, v.Sp, v.S, acc);
         if (lv) {
 #pragma unroll
             for (int cc = 0; cc < TC; ++cc)
@@ -129,8 +135,9 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
 }
 
 // One tile of TC cells (TC a multiple of 16) starting at cell c0; sH holds
-// TC x Sp floats of LDS.  Ends with every thread past its last read of sH.
-template <int TC, int NTW>
+// fused_lds_bytes(TC, Sp) bytes of LDS.  Ends with every thread past its last
+// read of the tile's LDS.
+template <int MODE, int TC, int NTW>
 __device__ __forceinline__ void fused_tile(const PlanView& v, int64_t c0, int64_t C,
                                            const float* __restrict__ J, int64_t ldj,
                                            const float* __restrict__ m, float* __restrict__ T,
@@ -138,9 +145,9 @@ __device__ __forceinline__ void fused_tile(const PlanView& v, int64_t c0, int64_
                                            dust_counters* cnt, float* sH) {
 #pragma unroll
     for (int mb = 0; mb < TC / 16; ++mb)
-        fused_absorb<NTW>(v, c0 + 16 * mb, C, J, ldj, sH + 16 * mb * v.Sp);
+        fused_absorb<MODE, NTW>(v, c0 + 16 * mb, C, J, ldj, sH + 16 * mb * v.Sp);
     __syncthreads();
-    fused_solve_emit<TC>(v, c0, C, m, T, ldt, L, ldl, cnt, sH);
+    fused_solve_emit<MODE, TC>(v, c0, C, m, T, ldt, L, ldl, cnt, sH);
     __syncthreads();
 }
 

@@ -47,13 +47,12 @@ struct PlanView {
     const float* em;       // w C c1 lam^-5 2^-ge (FP32): the emission weights
     float escale;          // 2^ge
     // float64 tables of the mixed solve
-    const double* kd;      // [S][NL] K' (FP64) for the exact fallback
-    const double* lamd;    // [NL] lam (FP64)
-    const double* lty;     // [S][N] ln P'(T_k)
-    const double* ltd;     // [S][N] d ln P' / d ln T at T_k
-    const uint16_t* kidx;  // [S][M] table interval at uniform steps of ln P'
-    const double* ylo;     // [S] lty[s][0]
-    const double* yhi;     // [S] lty[s][N-1]
+    const double* kdb;     // [S][NL] K' c1 lam^-5 (FP64): exact power weights
+    const double* c2l;     // [NL] c2 / lam (FP64)
+    const double2* fwd;    // [S][N] (y_k, h d_k): y_k = ln P'(T_k), d_k = d ln P'/d ln T
+    const double2* inv;    // [S][M] (ln T, dy * d ln T/dy) at uniform steps of y
+    const double* ylo;     // [S] y_0
+    const double* yhi;     // [S] y_{N-1}
     const double* dyinv;   // [S] (M - 1) / (yhi - ylo)
     int N, M;
     double lnTmin, hstep;  // ln T_k = lnTmin + k hstep
@@ -74,8 +73,8 @@ struct dust_plan {
     // derived device tables
     float *d_nu, *d_hscale, *d_hinv, *d_gs, *d_kf, *d_kb, *d_em;
     __bf16 *d_khi, *d_klo;
-    double *d_kd, *d_lty, *d_ltd, *d_ylo, *d_yhi, *d_dyinv;
-    uint16_t* d_kidx;
+    double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv;
+    double2 *d_fwd, *d_inv;
     dust::PlanView view;
 };
 

@@ -27,11 +27,12 @@ __global__ __launch_bounds__(256) void solve_mixed_kernel(PlanView v, int64_t C,
                                                           int64_t ldh, float* __restrict__ T,
                                                           int64_t ldt, dust_counters* cnt) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= C * v.S) return;
-    const int64_t c = i / v.S;
-    const int s = (int)(i - c * v.S);
-    const double hs = (double)H[c * ldh + s] * (double)v.hscale[s];
-    T[c * ldt + s] = solve_table_f64(v, s, hs, cnt);
+    const bool active = i < C * v.S;  // every lane stays for the wave-wide fallback
+    const int64_t c = active ? i / v.S : 0;
+    const int s = active ? (int)(i - c * v.S) : 0;
+    const double hs = active ? (double)H[c * ldh + s] * (double)v.hscale[s] : 0.0;
+    const float t = wave_solve_mixed(v, active, s, hs, cnt);
+    if (active) T[c * ldt + s] = t;
 }
 
 }  // namespace
