@@ -163,7 +163,22 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 launches), to "
+                         "calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes")
     args = ap.parse_args()
+
+    if args.copy_calibration_mb:
+        import torch
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -209,6 +224,12 @@ def main():
     torch.cuda.synchronize()
     mixed_cnt = cnt.cpu().tolist()
     mixed_err = check_sample(grid, J, params.m_dust, T, L)
+
+    log("timing mixed path, two-kernel fused form")
+    pm2 = dust.Plan(grid, "mixed", fused_kernels=2)
+    f2_stages = [("prepare", lambda: pm2.prepare()),
+                 ("fused2", lambda: pm2.fused(J, m, T, L, counters=cnt))]
+    f2_ms, f2_k = time_steps(torch, f2_stages, args.steps, args.warmup)
 
     log("timing mixed path as three launches")
     sep_stages = [("prepare", lambda: pm.prepare()),
@@ -275,6 +296,8 @@ def main():
                        "counters": dict(zip(["nonfinite", "unconverged", "out_of_table"], plain_cnt)),
                        "dtype": "f32",
                        "emit_Gterm_per_s": terms / (plain_k["emit"] * 1e-3) / 1e9},
+        "mixed_fused_two_kernels": {"ms_per_step": f2_ms, "stages_ms": f2_k,
+                                    "value": pairs / (f2_ms * 1e-3)},
         "mixed_three_launches": {"ms_per_step": sep_ms, "stages_ms": sep_k,
                                  "value": pairs / (sep_ms * 1e-3)},
         "mixed_over_plain": value / plain_value,

@@ -87,7 +87,10 @@ typedef struct {
     int32_t maxit;     /* plain: Newton iteration cap, default 50 */
     double tol;        /* plain: stop when |P(T)/H - 1| <= tol, default 1e-5 */
     int32_t ltab_n;    /* mixed: table points per grain, default 4096 (>= 16) */
-    int32_t reserved;  /* must be 0 */
+    int32_t fused_kernels; /* dust_run_fused: 0 = library choice, 1 = one kernel
+                              (absorb, solve and emit per cell tile), 2 = two
+                              kernels (absorb + solve per tile, T written once;
+                              then emit).  H never reaches device memory. */
     double ltab_tmin;  /* mixed: lowest tabulated T (K), default 2.7 */
     double ltab_tmax;  /* mixed: highest tabulated T (K), default 3000 */
 } dust_options;

@@ -75,7 +75,8 @@ dust_status resolve_options(const dust_options* in, dust_options* o) {
     if (d.ltab_n < 0 || (d.ltab_n > 0 && d.ltab_n < 16) || d.ltab_n > MAX_TABLE / 4)
         return set_error(DUST_EINVAL, "ltab_n must be 0 (default) or in [16, 16383]");
     if (d.ltab_n == 0) d.ltab_n = 4096;
-    if (d.reserved != 0) return set_error(DUST_EINVAL, "reserved must be 0");
+    if (d.fused_kernels < 0 || d.fused_kernels > 2)
+        return set_error(DUST_EINVAL, "fused_kernels must be 0, 1 or 2");
     if (d.ltab_tmin == 0.0) d.ltab_tmin = 2.7;
     if (d.ltab_tmax == 0.0) d.ltab_tmax = 3000.0;
     if (!(d.ltab_tmin > 0.0) || !(d.ltab_tmax > d.ltab_tmin) || !isfinite(d.ltab_tmax) ||
@@ -96,7 +97,7 @@ void free_plan(dust_plan* p) {
     void* ptrs[] = {p->d_lam, p->d_dlam, p->d_cabs, p->d_w,   p->d_size, p->d_es,   p->d_nu,
                     p->d_hscale, p->d_hinv, p->d_gs, p->d_kf,  p->d_kb,   p->d_em,   p->d_khi,
                     p->d_klo, p->d_kdb,  p->d_c2l,  p->d_fwd, p->d_inv, p->d_ylo,  p->d_yhi,
-                    p->d_dyinv};
+                    p->d_dyinv, p->d_texp, p->d_lntab};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -164,10 +165,13 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_error(e, "hipGetDevice");
     int max_lds = 65536;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (emit_lds_bytes(16, Sp) > (size_t)max_lds)
+    if (emit_lds_bytes(16, Sp) > (size_t)max_lds) {
+        int lim = 16;
+        while (emit_lds_bytes(16, lim + 16) <= (size_t)max_lds) lim += 16;
         return set_error(DUST_EUNSUPPORTED,
                          "n_grains too large for one emission tile in LDS on this device (limit " +
-                             std::to_string(max_lds / (16 * 5)) + ")");
+                             std::to_string(lim) + ")");
+    }
 
     dust_plan* p = new dust_plan;
     memset(p, 0, sizeof *p);
@@ -176,7 +180,7 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     p->NL = NL; p->S = S; p->NLp = NLp; p->Sp = Sp;
     p->ge = ge;
     p->N = o.ltab_n;
-    p->M = o.ltab_n;
+    p->M = o.ltab_n < 256 ? o.ltab_n : 256;  // inverse-table nodes (a start for Newton only)
     p->lnTmin = log(o.ltab_tmin);
     p->hstep = (log(o.ltab_tmax) - log(o.ltab_tmin)) / (p->N - 1);
     const bool mixed = o.mode == DUST_MIXED;
@@ -209,6 +213,8 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
         ALLOC(p->d_ylo, S);
         ALLOC(p->d_yhi, S);
         ALLOC(p->d_dyinv, S);
+        ALLOC(p->d_texp, p->N);
+        ALLOC(p->d_lntab, 256);
     }
 #undef ALLOC
 
@@ -223,6 +229,24 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
         {p->d_hinv, hinv.data(), sizeof(float) * Sp},
         {p->d_gs, gs.data(), sizeof(float) * Sp},
     };
+    // Static helper tables of the mixed lookup (they depend only on the
+    // table range): T_k, and ln c_i, 1/c_i for the 256 mantissa intervals.
+    std::vector<double> texp;
+    std::vector<double2> lntab;
+    if (mixed) {
+        texp.resize(p->N);
+        for (int k = 0; k < p->N; ++k) texp[k] = exp(p->lnTmin + k * p->hstep);
+        lntab.resize(256);
+        for (int i = 0; i < 256; ++i) {
+            const double c = 1.0 + i / 256.0;
+            lntab[i] = make_double2(log(c), 1.0 / c);
+        }
+        if ((e = hipMemcpy(p->d_texp, texp.data(), sizeof(double) * p->N, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->d_lntab, lntab.data(), sizeof(double2) * 256, hipMemcpyHostToDevice)) != hipSuccess) {
+            free_plan(p);
+            return hip_error(e, "hipMemcpy (lookup tables)");
+        }
+    }
     for (const Up& u : ups) {
         if ((e = hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice)) != hipSuccess) {
             free_plan(p);
@@ -256,6 +280,9 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     v.M = p->M;
     v.lnTmin = p->lnTmin;
     v.hstep = p->hstep;
+    v.inv_hstep = 1.0 / p->hstep;
+    v.texp = p->d_texp;
+    v.lntab = p->d_lntab;
 
     if ((e = launch_prepare(p, nullptr)) != hipSuccess) {
         free_plan(p);
@@ -355,7 +382,11 @@ dust_status dust_run_fused(dust_plan* p, int64_t C, const float* J, int64_t ldj,
     if ((st = check_buf(L, ldl, p->NL, C, "L")) != DUST_OK) return st;
     if (m && ((uintptr_t)m & 3u)) return set_error(DUST_EINVAL, "m_dust is not 4-byte aligned");
     if (cnt && ((uintptr_t)cnt & 7u)) return set_error(DUST_EINVAL, "counters must be 8-byte aligned");
-    hipError_t e = launch_fused(p->view, C, J, ldj, m, T, ldt, L, ldl, cnt, (hipStream_t)stream);
+    hipError_t e = (p->opt.fused_kernels == 2)
+                       ? launch_absorb_solve(p->view, C, J, ldj, T, ldt, cnt, (hipStream_t)stream)
+                       : launch_fused(p->view, C, J, ldj, m, T, ldt, L, ldl, cnt, (hipStream_t)stream);
+    if (e == hipSuccess && p->opt.fused_kernels == 2)
+        e = launch_emit(p->view, C, T, ldt, m, L, ldl, (hipStream_t)stream);
     return e == hipSuccess ? DUST_OK : hip_error(e, "fused launch");
 }
 

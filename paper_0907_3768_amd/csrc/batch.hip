@@ -44,7 +44,7 @@ template <int TC, int NTW>
 __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__ grids,
                                                     const int2* __restrict__ items, int n_items,
                                                     unsigned int* counter, dust_counters* cnt) {
-    extern __shared__ float sTile[];  // emit_lds_bytes(TC, Sp max)
+    extern __shared__ float sTile[];  // fused_lds_bytes(TC, Sp max)
     __shared__ int sItem;
     for (;;) {
         if (threadIdx.x == 0) sItem = (int)atomicAdd(counter, 1u);
@@ -114,7 +114,7 @@ hipError_t enqueue(const dust_batch* b, const Candidate& c, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int blocks = std::max(1, std::min(n_items, b->n_cu * c.per_cu));
-    const size_t lds = emit_lds_bytes(c.tc, b->sp_max);
+    const size_t lds = fused_lds_bytes(c.tc, b->sp_max);
     hipLaunchKernelGGL(kernel_for(c.tc, b->ntw), dim3(blocks), dim3(256), lds, st,
                        (const GridArgs*)b->d_grids, items, n_items, b->d_counter, b->counters);
     return hipGetLastError();
@@ -235,7 +235,7 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     std::vector<Candidate> cands;
     for (int tc : {16, 32})
         for (int per_cu : {1, 2, 4, 8}) {
-            const size_t lds = emit_lds_bytes(tc, sp_max);
+            const size_t lds = fused_lds_bytes(tc, sp_max);
             if (lds <= (size_t)max_lds && lds * per_cu <= 160u * 1024u)
                 cands.push_back(Candidate{tc, per_cu});
         }

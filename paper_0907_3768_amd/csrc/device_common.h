@@ -169,24 +169,71 @@ __device__ inline double wave_solve_exact_f64(const PlanView& v, int s, double h
 }
 
 // ---------------------------------------------------------------------------
-// Mixed solve of Eq. 7 from the grain's FP64 tables.  y = ln H' is located in
-// the inverse table (uniform in y: no search), whose cubic Hermite gives a
-// starting ln T; the forward table interval that holds it then gives the
-// cubic Hermite interpolant p(theta) of y(ln T), on which FP64 Newton steps
-// polish ln T.  Each table read is one 32-byte pair of double2.
-// Returns 0 with *T set, or, for a pair the table does not cover, a pending
-// code with *lnT0 a starting point for the exact solve:
-//   1: below the table, 2: above it, 3: the grain's table is not finite.
+// Cubic through four consecutive FP64 table values y0..y3 at unit-spaced
+// nodes 0..3, in Newton's divided-difference form, at x; *dp = d/dx.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double hermite(double t, double y0, double m0, double y1, double m1,
-                                          double* dp) {
+__device__ __forceinline__ double cubic4(double x, double y0, double y1, double y2, double y3,
+                                         double* dp) {
+    const double d1 = y1 - y0;
+    const double d2 = 0.5 * (y2 - 2.0 * y1 + y0);
+    const double d3 = (y3 - 3.0 * (y2 - y1) - y0) * (1.0 / 6.0);
+    const double xm1 = x - 1.0, xm2 = x - 2.0;
+    *dp = d1 + (x + xm1) * d2 + (x * xm1 + x * xm2 + xm1 * xm2) * d3;
+    return y0 + x * (d1 + xm1 * (d2 + xm2 * d3));
+}
+
+// First node of the 4-point stencil for interval [k, k+1] of an N-point table.
+__device__ __forceinline__ int stencil_start(int k, int N) {
+    const int j0 = k - 1;
+    return j0 < 0 ? 0 : (j0 > N - 4 ? N - 4 : j0);
+}
+
+// ---------------------------------------------------------------------------
+// Cubic Hermite on [0, 1] (inverse table).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double hermite(double t, double y0, double m0, double y1, double m1) {
     const double t2 = t * t, t3 = t2 * t;
-    *dp = (6.0 * t2 - 6.0 * t) * (y0 - y1) + (3.0 * t2 - 4.0 * t + 1.0) * m0 +
-          (3.0 * t2 - 2.0 * t) * m1;
     return (2.0 * t3 - 3.0 * t2 + 1.0) * y0 + (t3 - 2.0 * t2 + t) * m0 +
            (3.0 * t2 - 2.0 * t3) * y1 + (t3 - t2) * m1;
 }
 
+// ---------------------------------------------------------------------------
+// ln x for a positive finite double x whose mantissa has at most 24
+// significant bits (an FP32 value times a power of two): x = 2^E M,
+// M = c_i (1 + r) with c_i = 1 + i/256 from the top mantissa bits, and
+// ln(1 + r) from its series to r^6 (|r| < 2^-8: truncation < 2e-18).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ln_f32_value(double x, const double2* __restrict__ lntab) {
+    const double m = __builtin_amdgcn_frexp_mant(x);        // [0.5, 1)
+    const int e = __builtin_amdgcn_frexp_exp(x) - 1;
+    const double M = 2.0 * m;                               // [1, 2)
+    const int i = (int)((M - 1.0) * 256.0);
+    const double2 t = lntab[i];
+    const double r = (M - (1.0 + i * (1.0 / 256.0))) * t.y;  // M - c_i is exact
+    const double lr = r * (1.0 + r * (-0.5 + r * (1.0 / 3.0 + r * (-0.25 + r * (0.2 - r * (1.0 / 6.0))))));
+    return (double)e * 6.93147180369123816490e-01 + ((double)e * 1.90821492927058770002e-10 +
+                                                     (t.x + lr));
+}
+
+// 1 / x with v_rcp_f64 and one Newton-Raphson refinement.
+__device__ __forceinline__ double rcp_f64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed solve of Eq. 7 from the grain's FP64 tables.  y = ln H' is located in
+// the inverse table (ln T at uniform steps of y: no search), whose cubic
+// Hermite gives a starting ln T within about 1e-6; the forward table
+// y_k = ln P'(T_k) around it gives the cubic through four neighbouring
+// points, on which one FP64 Newton step polishes ln T (the start is within
+// about 1e-3 of a table step, so the step leaves an error near 1e-12 of one).
+// T = T_k e^d with T_k from a table and e^d, 0 <= d < hstep, from its series.
+// Returns 0 with *T set, or, for a pair the table does not cover, a pending
+// code with *lnT0 a starting point for the exact solve:
+//   1: below the table, 2: above it, 3: the grain's table is not finite.
+// ---------------------------------------------------------------------------
 __device__ inline int table_lookup_f64(const PlanView& v, int s, double hs, float* T,
                                        double* lnT0, dust_counters* cnt) {
     if (!(hs >= 0.0) || __builtin_isinf(hs)) {
@@ -195,39 +242,37 @@ __device__ inline int table_lookup_f64(const PlanView& v, int s, double hs, floa
         return 0;
     }
     if (hs == 0.0) { *T = 0.0f; return 0; }
-    const double y = log(hs);
+    const double y = ln_f32_value(hs, v.lntab);
     const double ylo = v.ylo[s], yhi = v.yhi[s];
     const int N = v.N, M = v.M;
-    const double2* f = v.fwd + (int64_t)s * N;
+    const double* f = v.fwd + (int64_t)s * N;
     if (!(__builtin_isfinite(ylo) && __builtin_isfinite(yhi))) { *lnT0 = 0.0; return 3; }
-    if (y < ylo) {
-        *lnT0 = v.lnTmin + (y - ylo) * v.hstep / f[0].y;
+    if (y < ylo) {  // extrapolate with the slope of the first interval
+        *lnT0 = v.lnTmin + (y - ylo) * v.hstep / (f[1] - f[0]);
         return 1;
     }
     if (y > yhi) {
-        *lnT0 = v.lnTmin + (N - 1) * v.hstep + (y - yhi) * v.hstep / f[N - 1].y;
+        *lnT0 = v.lnTmin + (N - 1) * v.hstep + (y - yhi) * v.hstep / (f[N - 1] - f[N - 2]);
         return 2;
     }
-    // inverse table: ln T(y) at uniform nodes
+    // inverse table: ln T(y) at uniform nodes, as a position in table steps
     const double uj = (y - ylo) * v.dyinv[s];
     int j = (int)uj;
     j = j < 0 ? 0 : (j > M - 2 ? M - 2 : j);
     const double2* g = v.inv + (int64_t)s * M + j;
     const double2 g0 = g[0], g1 = g[1];
-    double dummy;
-    const double lnT_start = hermite(uj - j, g0.x, g0.y, g1.x, g1.y, &dummy);
-    // forward interval holding the start, then Newton on its cubic
-    const double kt = (lnT_start - v.lnTmin) / v.hstep;
+    const double kt = (hermite(uj - j, g0.x, g0.y, g1.x, g1.y) - v.lnTmin) * v.inv_hstep;
     int k = (int)kt;
     k = k < 0 ? 0 : (k > N - 2 ? N - 2 : k);
-    const double2 a = f[k], b = f[k + 1];
-    double th = kt - k;
-    for (int it = 0; it < 2; ++it) {
-        double dp;
-        const double p = hermite(th, a.x, a.y, b.x, b.y, &dp);
-        th -= (p - y) / dp;
-    }
-    *T = (float)exp(v.lnTmin + ((double)k + th) * v.hstep);
+    const int j0 = stencil_start(k, N);
+    double dp;
+    const double p = cubic4(kt - j0, f[j0], f[j0 + 1], f[j0 + 2], f[j0 + 3], &dp);
+    const double pos = kt - (p - y) * rcp_f64(dp);  // position in table steps
+    int kk = (int)pos;
+    kk = kk < 0 ? 0 : (kk > N - 1 ? N - 1 : kk);
+    const double d = (pos - kk) * v.hstep;
+    const double ed = 1.0 + d * (1.0 + d * (0.5 + d * (1.0 / 6.0 + d * (1.0 / 24.0 + d * (1.0 / 120.0)))));
+    *T = (float)(v.texp[kk] * ed);
     return 0;
 }
 
@@ -273,11 +318,11 @@ __device__ inline float wave_solve_mixed(const PlanView& v, bool active, int s, 
 //
 // LDS tile (filled by the caller):
 //   sInvT  [TC][Sp]  1/T per cell and grain (+inf for T = 0, NaN for bad T);
-//   sChunk [Sp/4][TC] bits of the smallest 1/T over each group of 4 grains
+//   sChunk [Sp/8][TC] bits of the smallest 1/T over each group of 8 grains
 //                     (0 when the group holds a NaN).
 // Both are read with wave-uniform addresses (LDS broadcast).
 //
-// For each (4-grain group, cell) the wave picks one evaluation, uniformly, by
+// For each (8-grain group, cell) the wave picks one evaluation, uniformly, by
 // comparing the group's hottest grain at the wave's longest wavelength
 // (smallest t over the wave's lanes) with three thresholds:
 //   t >= 150      every term is exactly 0 in FP32 (2^-150 underflows): skip;
@@ -288,25 +333,32 @@ __device__ inline float wave_solve_mixed(const PlanView& v, bool active, int s, 
 // order is that of unsigned integers), so they run on the scalar unit.
 // Costs per term: 0, 2 VALU + 1 exp, 3 VALU + 1 exp, 3 VALU + exp + rcp.
 // ---------------------------------------------------------------------------
-// LDS bytes of an emission tile of TC cells: sInvT plus sChunk.
-__host__ __device__ constexpr size_t emit_lds_bytes(int TC, int Sp) {
-    return (size_t)TC * (size_t)Sp * sizeof(float) + (size_t)(Sp / 4) * TC * sizeof(uint32_t);
+constexpr int EMIT_GROUP = 8;  // grains per class decision
+
+__device__ __forceinline__ bool any_nan8(const float4& a, const float4& b) {
+    return __builtin_isnan(a.x) || __builtin_isnan(a.y) || __builtin_isnan(a.z) ||
+           __builtin_isnan(a.w) || __builtin_isnan(b.x) || __builtin_isnan(b.y) ||
+           __builtin_isnan(b.z) || __builtin_isnan(b.w);
 }
 
-__device__ __forceinline__ uint32_t chunk_min_bits(float a, float b, float c, float d) {
-    if (__builtin_isnan(a) || __builtin_isnan(b) || __builtin_isnan(c) || __builtin_isnan(d))
-        return 0u;  // forces the exact form, which propagates the NaN
-    return __float_as_uint(fminf(fminf(a, b), fminf(c, d)));
+// LDS bytes of an emission tile of TC cells: sInvT plus sChunk.
+__host__ __device__ constexpr size_t emit_lds_bytes(int TC, int Sp) {
+    return (size_t)TC * (size_t)Sp * sizeof(float) +
+           (size_t)(Sp / EMIT_GROUP) * TC * sizeof(uint32_t);
 }
 
 // Fill sChunk from sInvT (all threads of the block; caller synchronises).
 template <int TC>
 __device__ __forceinline__ void fill_chunk_min(const float* sInvT, uint32_t* sChunk, int Sp) {
-    const int SC = Sp >> 2;
+    const int SC = Sp / EMIT_GROUP;
     for (int i = threadIdx.x; i < TC * SC; i += blockDim.x) {
         const int ch = i / TC, cc = i - ch * TC;
-        const float4 t = *reinterpret_cast<const float4*>(sInvT + cc * Sp + 4 * ch);
-        sChunk[i] = chunk_min_bits(t.x, t.y, t.z, t.w);
+        const float4 a = *reinterpret_cast<const float4*>(sInvT + cc * Sp + EMIT_GROUP * ch);
+        const float4 b = *reinterpret_cast<const float4*>(sInvT + cc * Sp + EMIT_GROUP * ch + 4);
+        const float m = fminf(fminf(fminf(a.x, a.y), fminf(a.z, a.w)),
+                              fminf(fminf(b.x, b.y), fminf(b.z, b.w)));
+        // a NaN forces the exact form, which propagates it
+        sChunk[i] = any_nan8(a, b) ? 0u : __float_as_uint(m);
     }
 }
 
@@ -322,44 +374,49 @@ __device__ __forceinline__ void emit_accumulate(const float* __restrict__ em, in
     const uint32_t thr_y2 = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(12.0f / u_wave_min));
 #pragma unroll
     for (int cc = 0; cc < TC; ++cc) acc[cc] = 0.0f;
-    for (int s = 0; s < S; s += 4) {
-        const float e0 = em[(int64_t)(s + 0) * NLp];
-        const float e1 = em[(int64_t)(s + 1) * NLp];
-        const float e2 = em[(int64_t)(s + 2) * NLp];
-        const float e3 = em[(int64_t)(s + 3) * NLp];
-        const uint32_t* cmrow = sChunk + (s >> 2) * TC;
+    for (int s = 0; s < S; s += EMIT_GROUP) {
+        float e[EMIT_GROUP];
+#pragma unroll
+        for (int g = 0; g < EMIT_GROUP; ++g) e[g] = em[(int64_t)(s + g) * NLp];
+        const uint32_t* cmrow = sChunk + (s / EMIT_GROUP) * TC;
 #pragma unroll
         for (int c4 = 0; c4 < TC; c4 += 4) {
             const uint4 cm4 = *reinterpret_cast<const uint4*>(cmrow + c4);
+            float4 ia[4], ib[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ia[k] = *reinterpret_cast<const float4*>(sInvT + (c4 + k) * Sp + s);
+                ib[k] = *reinterpret_cast<const float4*>(sInvT + (c4 + k) * Sp + s + 4);
+            }
             const uint32_t cms[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(cm4.x),
                                      (uint32_t)__builtin_amdgcn_readfirstlane(cm4.y),
                                      (uint32_t)__builtin_amdgcn_readfirstlane(cm4.z),
                                      (uint32_t)__builtin_amdgcn_readfirstlane(cm4.w)};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int cc = c4 + k;
                 const uint32_t cm = cms[k];
                 if (cm >= thr_skip) continue;
-                const float4 it = *reinterpret_cast<const float4*>(sInvT + cc * Sp + s);
-                float a = acc[cc];
+                const float it[EMIT_GROUP] = {ia[k].x, ia[k].y, ia[k].z, ia[k].w,
+                                              ib[k].x, ib[k].y, ib[k].z, ib[k].w};
+                float a = acc[c4 + k];
                 if (cm >= thr_y) {
-                    a = fmaf(e0, __builtin_amdgcn_exp2f(nu * it.x), a);
-                    a = fmaf(e1, __builtin_amdgcn_exp2f(nu * it.y), a);
-                    a = fmaf(e2, __builtin_amdgcn_exp2f(nu * it.z), a);
-                    a = fmaf(e3, __builtin_amdgcn_exp2f(nu * it.w), a);
+#pragma unroll
+                    for (int g = 0; g < EMIT_GROUP; ++g)
+                        a = fmaf(e[g], __builtin_amdgcn_exp2f(nu * it[g]), a);
                 } else if (cm >= thr_y2) {
-                    float y;
-                    y = __builtin_amdgcn_exp2f(nu * it.x); a = fmaf(e0, fmaf(y, y, y), a);
-                    y = __builtin_amdgcn_exp2f(nu * it.y); a = fmaf(e1, fmaf(y, y, y), a);
-                    y = __builtin_amdgcn_exp2f(nu * it.z); a = fmaf(e2, fmaf(y, y, y), a);
-                    y = __builtin_amdgcn_exp2f(nu * it.w); a = fmaf(e3, fmaf(y, y, y), a);
+#pragma unroll
+                    for (int g = 0; g < EMIT_GROUP; ++g) {
+                        const float y = __builtin_amdgcn_exp2f(nu * it[g]);
+                        a = fmaf(e[g], fmaf(y, y, y), a);
+                    }
                 } else {
-                    a = fmaf(e0, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it.x)) - 1.0f), a);
-                    a = fmaf(e1, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it.y)) - 1.0f), a);
-                    a = fmaf(e2, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it.z)) - 1.0f), a);
-                    a = fmaf(e3, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it.w)) - 1.0f), a);
+#pragma unroll
+                    for (int g = 0; g < EMIT_GROUP; ++g)
+                        a = fmaf(e[g],
+                                 __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it[g])) - 1.0f),
+                                 a);
                 }
-                acc[cc] = a;
+                acc[c4 + k] = a;
             }
         }
     }

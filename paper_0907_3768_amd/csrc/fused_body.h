@@ -8,68 +8,116 @@ namespace dust {
 
 constexpr int FUSED_TC = 16;  // default cells per tile (one MFMA M-block)
 
+// LDS staging of one 16 x 32 chunk of J per K-step, double-buffered.
+// Mixed mode keeps it as bf16 hi and lo halves (rows padded to 40 values),
+// plain mode as FP32 (rows padded to 36 values).  The padding spreads the 16
+// lanes of each 128-bit read phase over distinct banks.
+constexpr int STAGE_ROW_BF16 = 40;
+constexpr int STAGE_ROW_F32 = 36;
+constexpr int STAGE_BUF_BYTES = 2 * 16 * STAGE_ROW_BF16 * 2;  // >= 16 * 36 * 4
+constexpr int STAGE_BYTES = 2 * STAGE_BUF_BYTES;
+
 // Phase 1: heating of a 16-cell block into sH[16][Sp] (rows of the tile's
-// LDS array) in the plan's scaled units H' = H 2^es.  Wave w computes grain
-// tiles w, w+4, ... (NTW of them).
+// LDS array) in the plan's scaled units H' = H 2^es, on the MFMA units.
+//
+// Per K-step of 32 wavelengths the block loads the 16 x 32 chunk of J with
+// coalesced loads (thread t: row t/16, columns 2(t mod 16) and +1), splits it
+// (mixed: bf16 hi + lo) into LDS, and each wave multiplies it with its grain
+// tiles w, w+4, ... (NTW of them).  The next chunk of J is loaded into
+// registers while the current MFMAs run.
+//
+// K-order: lane (row = lane mod 16, q = lane / 16) supplies wavelengths
+// k0 + 8q .. k0 + 8q + 7 to both operands -- one 16x16x32 bf16 MFMA, or eight
+// 16x16x4 FP32 MFMAs in which MFMA i takes k0 + 8q + i.  Any assignment of
+// wavelengths to MFMA k-slots gives the same sum as long as both operands
+// use it.
 template <int MODE, int NTW>
 __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int64_t C,
                                              const float* __restrict__ J, int64_t ldj,
-                                             float* sH) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+                                             float* sH, char* sStage) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
-    const int64_t c = c0 + row;
-    const bool cv = c < C;
-    const float* jr = J + (cv ? c : 0) * ldj;
     const int tiles = v.Sp / 16;
+    // loader role: 256 threads x 2 floats = one 16 x 32 chunk
+    const int lrow = tid >> 4, lcol = (tid & 15) * 2;
+    const bool lrow_ok = c0 + lrow < C;
+    const float* jl = J + (lrow_ok ? c0 + lrow : 0) * ldj;
+
     f32x4 acc[NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    if constexpr (MODE == DUST_MIXED) {
-        for (int k0 = 0; k0 < v.NL; k0 += 32) {
-            const int kb = k0 + kq * 8;
-            float x[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) x[i] = (cv && kb + i < v.NL) ? jr[kb + i] : 0.0f;
-            bf16x8 ahi, alo;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                ahi[i] = (__bf16)x[i];
-                alo[i] = (__bf16)(x[i] - (float)ahi[i]);
-            }
+    auto load_j = [&](int k0, float& x0, float& x1) {
+        const int k = k0 + lcol;
+        x0 = (lrow_ok && k < v.NL) ? jl[k] : 0.0f;
+        x1 = (lrow_ok && k + 1 < v.NL) ? jl[k + 1] : 0.0f;
+    };
+    auto store_j = [&](int buf, float x0, float x1) {
+        char* base = sStage + buf * STAGE_BUF_BYTES;
+        if constexpr (MODE == DUST_MIXED) {
+            // [hi|lo][16 rows][STAGE_ROW_BF16] bf16; a pair of columns per 32-bit store
+            typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+            const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+            const bf16x2 hi = {h0, h1};
+            const bf16x2 lo = {(__bf16)(x0 - (float)h0), (__bf16)(x1 - (float)h1)};
+            bf16x2* b = reinterpret_cast<bf16x2*>(base);
+            b[(lrow * STAGE_ROW_BF16 + lcol) / 2] = hi;
+            b[(16 * STAGE_ROW_BF16 + lrow * STAGE_ROW_BF16 + lcol) / 2] = lo;
+        } else {
+            float2* b = reinterpret_cast<float2*>(base);
+            b[(lrow * STAGE_ROW_F32 + lcol) / 2] = make_float2(x0, x1);
+        }
+    };
+
+    const int nsteps = (v.NL + 31) / 32;
+    float x0, x1;
+    load_j(0, x0, x1);
+    store_j(0, x0, x1);
+    __syncthreads();
+    for (int step = 0; step < nsteps; ++step) {
+        const int k0 = step * 32;
+        const int buf = step & 1;
+        if (step + 1 < nsteps) load_j(k0 + 32, x0, x1);  // prefetch the next chunk
+        if constexpr (MODE == DUST_MIXED) {
+            const __bf16* b = reinterpret_cast<const __bf16*>(sStage + buf * STAGE_BUF_BYTES);
+            const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(b + row * STAGE_ROW_BF16 + kq * 8);
+            const bf16x8 alo = *reinterpret_cast<const bf16x8*>(
+                b + 16 * STAGE_ROW_BF16 + row * STAGE_ROW_BF16 + kq * 8);
 #pragma unroll
             for (int t = 0; t < NTW; ++t) {
                 const int tile = wave + 4 * t;
                 if (tile < tiles) {
-                    const int s = tile * 16 + row;
-                    const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(v.khi + (int64_t)s * v.NLp + kb);
-                    const bf16x8 blo = *reinterpret_cast<const bf16x8*>(v.klo + (int64_t)s * v.NLp + kb);
+                    const int64_t o = (int64_t)(tile * 16 + row) * v.NLp + k0 + kq * 8;
+                    const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(v.khi + o);
+                    const bf16x8 blo = *reinterpret_cast<const bf16x8*>(v.klo + o);
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[t], 0, 0, 0);
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[t], 0, 0, 0);
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[t], 0, 0, 0);
                 }
             }
-        }
-    } else {
-        for (int k0 = 0; k0 < v.NL; k0 += 32) {
-            float a[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = k0 + 4 * i + kq;
-                a[i] = (cv && k < v.NL) ? jr[k] : 0.0f;
-            }
+        } else {
+            const float* b = reinterpret_cast<const float*>(sStage + buf * STAGE_BUF_BYTES);
+            const float4 a0 = *reinterpret_cast<const float4*>(b + row * STAGE_ROW_F32 + kq * 8);
+            const float4 a1 = *reinterpret_cast<const float4*>(b + row * STAGE_ROW_F32 + kq * 8 + 4);
+            const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
             for (int t = 0; t < NTW; ++t) {
                 const int tile = wave + 4 * t;
                 if (tile < tiles) {
-                    const float* kr = v.kf + (int64_t)(tile * 16 + row) * v.NLp + k0 + kq;
+                    const float* kr = v.kf + (int64_t)(tile * 16 + row) * v.NLp + k0 + kq * 8;
+                    const float4 b0 = *reinterpret_cast<const float4*>(kr);
+                    const float4 b1 = *reinterpret_cast<const float4*>(kr + 4);
+                    const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
                     for (int i = 0; i < 8; ++i)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], kr[4 * i], acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[i], acc[t], 0, 0, 0);
                 }
             }
         }
+        if (step + 1 < nsteps) store_j(buf ^ 1, x0, x1);
+        __syncthreads();
     }
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
@@ -86,11 +134,9 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
 // (T to device memory, 1/T back into sH), then emit the tile's SEDs.  The
 // group minima of 1/T follow sH in LDS (see emit_accumulate).
 template <int MODE, int TC>
-__device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, int64_t C,
-                                                 const float* __restrict__ m,
-                                                 float* __restrict__ T, int64_t ldt,
-                                                 float* __restrict__ L, int64_t ldl,
-                                                 dust_counters* cnt, float* sH) {
+__device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64_t C,
+                                            float* __restrict__ T, int64_t ldt,
+                                            dust_counters* cnt, float* sH) {
     const int n = TC * v.Sp;
     // Same trip count for every lane: the mixed solve works wave-wide.
     for (int base = 0; base < n; base += blockDim.x) {
@@ -109,6 +155,16 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
         if (pair) T[c * ldt + s] = t;
         if (i < n) sH[i] = pair ? inv_temperature(t) : __builtin_inff();
     }
+}
+
+template <int MODE, int TC>
+__device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, int64_t C,
+                                                 const float* __restrict__ m,
+                                                 float* __restrict__ T, int64_t ldt,
+                                                 float* __restrict__ L, int64_t ldl,
+                                                 dust_counters* cnt, float* sH) {
+    const int n = TC * v.Sp;
+    fused_solve<MODE, TC>(v, c0, C, T, ldt, cnt, sH);
     __syncthreads();
     uint32_t* sChunk = reinterpret_cast<uint32_t*>(sH + n);
     fill_chunk_min<TC>(sH, sChunk, v.Sp);
@@ -134,18 +190,26 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
     }
 }
 
-// One tile of TC cells (TC a multiple of 16) starting at cell c0; sH holds
-// fused_lds_bytes(TC, Sp) bytes of LDS.  Ends with every thread past its last
-// read of the tile's LDS.
+// LDS bytes of a fused tile of TC cells: the emission tile (whose first
+// TC x Sp floats hold H' and then 1/T) plus the J staging buffers.
+__host__ __device__ constexpr size_t fused_lds_bytes(int TC, int Sp) {
+    return emit_lds_bytes(TC, Sp) + STAGE_BYTES;
+}
+
+// One tile of TC cells (TC a multiple of 16) starting at cell c0; lds holds
+// fused_lds_bytes(TC, Sp) bytes.  Ends with every thread past its last read
+// of the tile's LDS.
 template <int MODE, int TC, int NTW>
 __device__ __forceinline__ void fused_tile(const PlanView& v, int64_t c0, int64_t C,
                                            const float* __restrict__ J, int64_t ldj,
                                            const float* __restrict__ m, float* __restrict__ T,
                                            int64_t ldt, float* __restrict__ L, int64_t ldl,
-                                           dust_counters* cnt, float* sH) {
+                                           dust_counters* cnt, float* lds) {
+    float* sH = lds;
+    char* sStage = reinterpret_cast<char*>(lds) + emit_lds_bytes(TC, v.Sp);
 #pragma unroll
     for (int mb = 0; mb < TC / 16; ++mb)
-        fused_absorb<MODE, NTW>(v, c0 + 16 * mb, C, J, ldj, sH + 16 * mb * v.Sp);
+        fused_absorb<MODE, NTW>(v, c0 + 16 * mb, C, J, ldj, sH + 16 * mb * v.Sp, sStage);
     __syncthreads();
     fused_solve_emit<MODE, TC>(v, c0, C, m, T, ldt, L, ldl, cnt, sH);
     __syncthreads();

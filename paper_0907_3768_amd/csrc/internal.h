@@ -49,13 +49,16 @@ struct PlanView {
     // float64 tables of the mixed solve
     const double* kdb;     // [S][NL] K' c1 lam^-5 (FP64): exact power weights
     const double* c2l;     // [NL] c2 / lam (FP64)
-    const double2* fwd;    // [S][N] (y_k, h d_k): y_k = ln P'(T_k), d_k = d ln P'/d ln T
+    const double* fwd;     // [S][N] y_k = ln P'(T_k), T_k = exp(lnTmin + k hstep)
     const double2* inv;    // [S][M] (ln T, dy * d ln T/dy) at uniform steps of y
     const double* ylo;     // [S] y_0
     const double* yhi;     // [S] y_{N-1}
     const double* dyinv;   // [S] (M - 1) / (yhi - ylo)
     int N, M;
     double lnTmin, hstep;  // ln T_k = lnTmin + k hstep
+    double inv_hstep;
+    const double* texp;    // [N] T_k = exp(lnTmin + k hstep)
+    const double2* lntab;  // [256] (ln c_i, 1 / c_i), c_i = 1 + i / 256
 };
 
 }  // namespace dust
@@ -73,8 +76,8 @@ struct dust_plan {
     // derived device tables
     float *d_nu, *d_hscale, *d_hinv, *d_gs, *d_kf, *d_kb, *d_em;
     __bf16 *d_khi, *d_klo;
-    double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv;
-    double2 *d_fwd, *d_inv;
+    double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv, *d_fwd, *d_texp;
+    double2 *d_inv, *d_lntab;
     dust::PlanView view;
 };
 
@@ -92,6 +95,8 @@ hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ld
                         float* T, int64_t ldt, dust_counters* cnt, hipStream_t st);
 hipError_t launch_emit(const PlanView& v, int64_t C, const float* T, int64_t ldt,
                        const float* m, float* L, int64_t ldl, hipStream_t st);
+hipError_t launch_absorb_solve(const PlanView& v, int64_t C, const float* J, int64_t ldj,
+                               float* T, int64_t ldt, dust_counters* cnt, hipStream_t st);
 hipError_t launch_fused(const PlanView& v, int64_t C, const float* J, int64_t ldj,
                         const float* m, float* T, int64_t ldt, float* L, int64_t ldl,
                         dust_counters* cnt, hipStream_t st);

@@ -5,12 +5,12 @@
 //        a bf16 hi+lo pair; the solve weights K' c1 lam^-5; the emission
 //        weights w C c1 lam^-5 (Eq. 10 without the mass); the wavelength
 //        exponent table nu = -c2 log2(e) / lam.
-//  ltab  (mixed mode): per grain, y_k = ln P'(T_k) and d ln P'/d ln T at
-//        log-spaced T_k, in FP64, with P'(T) = sum_l K'_l B(lam_l, T)
-//        the right side of Eq. 7 in the plan's scaled units.
+//  ltab  (mixed mode): per grain, y_k = ln P'(T_k) at log-spaced T_k, in
+//        FP64, with P'(T) = sum_l K'_l B(lam_l, T) the right side of Eq. 7 in
+//        the plan's scaled units.
 //  inv   (mixed mode): the inverse function ln T(y) and its derivative at
-//        uniform steps of y, from Newton on the cubic Hermite interpolant of
-//        the forward table, so that a lookup starts next to its root.
+//        uniform steps of y, from Newton on the forward table's piecewise
+//        cubic, so that a lookup starts next to its root.
 #include "device_common.h"
 
 namespace dust {
@@ -55,34 +55,31 @@ __global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __r
     }
 }
 
-// One thread per (grain, table point).  Per term: one multiply, expm1, one
-// division; B = c1 lam^-5 / (e^x - 1) and T dB/dT = B x e^x / (e^x - 1).
-__global__ __launch_bounds__(256) void ltab_kernel(PlanView v, double2* fwd) {
+// One thread per (grain, table point).  Per term: one multiply, e^x - 1 and
+// one division; B = c1 lam^-5 / (e^x - 1).
+__global__ __launch_bounds__(256) void ltab_kernel(PlanView v, double* fwd) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (k >= v.N) return;
     const double invT = exp(-(v.lnTmin + k * v.hstep));
     const double* kdb = v.kdb + (int64_t)s * v.NL;
-    double P = 0.0, D = 0.0;
-    for (int l = 0; l < v.NL; ++l) {
-        const double x = v.c2l[l] * invT;
-        const double r = 1.0 / expm1_pos(x);  // 0 once e^x overflows
-        const double b = kdb[l] * r;
-        P += b;
-        D += b * x * (1.0 + r);
-    }
-    fwd[(int64_t)s * v.N + k] = make_double2(log(P), v.hstep * (D / P));
+    double P = 0.0;
+    for (int l = 0; l < v.NL; ++l)
+        P += kdb[l] / expm1_pos(v.c2l[l] * invT);  // 0 once e^x overflows
+    fwd[(int64_t)s * v.N + k] = log(P);
 }
 
-// One thread per (grain, inverse node): ln T at y_j = ylo + j dy.
-__global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double2* __restrict__ fwd,
+// One thread per (grain, inverse node): ln T at y_j = ylo + j dy, by Newton
+// on the forward table's cubic, and dy * d ln T / dy there.
+__global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double* __restrict__ fwd,
                                                   double2* inv, double* ylo, double* yhi,
                                                   double* dyinv) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (j >= v.M) return;
-    const double2* f = fwd + (int64_t)s * v.N;
-    const double y0 = f[0].x, y1 = f[v.N - 1].x;
+    const int N = v.N;
+    const double* f = fwd + (int64_t)s * N;
+    const double y0 = f[0], y1 = f[N - 1];
     const double dinv = (v.M - 1) / (y1 - y0);
     if (j == 0) {
         ylo[s] = y0;
@@ -91,25 +88,22 @@ __global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double2* __r
     }
     const double yj = (j == v.M - 1) ? y1 : y0 + j / dinv;
     // largest k in [0, N-2] with y_k <= yj
-    int lo = 0, hi = v.N - 2;
+    int lo = 0, hi = N - 2;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (f[mid].x <= yj) lo = mid; else hi = mid - 1;
+        if (f[mid] <= yj) lo = mid; else hi = mid - 1;
     }
-    const double2 a = f[lo], b = f[lo + 1];
-    double th = (b.x > a.x) ? (yj - a.x) / (b.x - a.x) : 0.0;
+    const int j0 = stencil_start(lo, N);
+    const double a0 = f[j0], a1 = f[j0 + 1], a2 = f[j0 + 2], a3 = f[j0 + 3];
+    double x = lo - j0 + ((f[lo + 1] > f[lo]) ? (yj - f[lo]) / (f[lo + 1] - f[lo]) : 0.0);
     double dp = 1.0;
     for (int it = 0; it < 4; ++it) {
-        const double t2 = th * th, t3 = t2 * th;
-        const double p = (2.0 * t3 - 3.0 * t2 + 1.0) * a.x + (t3 - 2.0 * t2 + th) * a.y +
-                         (3.0 * t2 - 2.0 * t3) * b.x + (t3 - t2) * b.y;
-        dp = (6.0 * t2 - 6.0 * th) * a.x + (3.0 * t2 - 4.0 * th + 1.0) * a.y +
-             (6.0 * th - 6.0 * t2) * b.x + (3.0 * t2 - 2.0 * th) * b.y;
-        th -= (p - yj) / dp;
-        th = th < 0.0 ? 0.0 : (th > 1.0 ? 1.0 : th);
+        const double p = cubic4(x, a0, a1, a2, a3, &dp);
+        x -= (p - yj) / dp;
     }
-    // d lnT / dy = hstep / (dp/dth), scaled by the node spacing dy = 1/dinv
-    inv[(int64_t)s * v.M + j] = make_double2(v.lnTmin + ((double)lo + th) * v.hstep,
+    cubic4(x, a0, a1, a2, a3, &dp);
+    // d lnT / dy = hstep / (dy/dx), scaled by the node spacing dy = 1/dinv
+    inv[(int64_t)s * v.M + j] = make_double2(v.lnTmin + ((double)j0 + x) * v.hstep,
                                              v.hstep / dp / dinv);
 }
 
@@ -128,7 +122,7 @@ hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g3((v.M + 255) / 256, v.S);
-    hipLaunchKernelGGL(inv_kernel, g3, dim3(256), 0, st, v, (const double2*)p->d_fwd, p->d_inv,
+    hipLaunchKernelGGL(inv_kernel, g3, dim3(256), 0, st, v, (const double*)p->d_fwd, p->d_inv,
                        p->d_ylo, p->d_yhi, p->d_dyinv);
     return hipGetLastError();
 }

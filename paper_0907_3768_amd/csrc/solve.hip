@@ -22,6 +22,7 @@ __global__ __launch_bounds__(256) void solve_plain_kernel(PlanView v, int64_t C,
                                       v.tol, v.maxit, cnt);
 }
 
+// One thread per (cell, grain) in row-major order: coalesced H and T.
 __global__ __launch_bounds__(256) void solve_mixed_kernel(PlanView v, int64_t C,
                                                           const float* __restrict__ H,
                                                           int64_t ldh, float* __restrict__ T,

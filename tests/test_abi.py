@@ -66,7 +66,7 @@ def _desc(nl=8, s=2, lam=None, cabs=None, size=None):
     ("bad_mode", dust.DUST_EINVAL),
     ("bad_ltab", dust.DUST_EINVAL),
     ("bad_trange", dust.DUST_EINVAL),
-    ("reserved", dust.DUST_EINVAL),
+    ("bad_fused_kernels", dust.DUST_EINVAL),
 ])
 def test_plan_create_rejects(L, case, expect):
     nl, s = 8, 2
@@ -98,8 +98,8 @@ def test_plan_create_rejects(L, case, expect):
         opt.ltab_n = 3
     if case == "bad_trange":
         opt.ltab_tmin, opt.ltab_tmax = 100.0, 50.0
-    if case == "reserved":
-        opt.reserved = 1
+    if case == "bad_fused_kernels":
+        opt.fused_kernels = 3
     d, keep = _desc(max(nl, 1), max(s, 1), lam if nl else None, cabs if s else None,
                     size if s else None)
     d.n_lambda, d.n_grains = nl, s

@@ -64,13 +64,14 @@ def _run(plan, J, m, path, counters=None):
 # --------------------------------------------------------------------------- small, full compare
 
 @pytest.mark.parametrize("mode", ["plain", "mixed"])
-@pytest.mark.parametrize("path", ["separate", "fused"])
+@pytest.mark.parametrize("path", ["separate", "fused", "fused2"])
 def test_small_full_compare(dev, mode, path):
     w = synth.WORKLOADS["small-1024x120x20"]
     g = w.grid()
     say(f"small-1024x120x20 mode={mode} path={path}")
     J, m = _inputs(g, w.n_cells, w.seed, dev)
-    plan = dust.Plan(g, mode)
+    plan = dust.Plan(g, mode, fused_kernels=2 if path == "fused2" else 1)
+    path = "fused" if path == "fused2" else path
     cnt = dust.new_counters(dev)
     H, T, L = _run(plan, J, m, path, cnt)
     res = check_against_oracle(g, _host(J), _host(m).astype(np.float64), _host(T), _host(L),
@@ -86,7 +87,7 @@ def test_small_full_compare(dev, mode, path):
 # --------------------------------------------------------------------------- ragged shapes, strides
 
 @pytest.mark.parametrize("mode", ["plain", "mixed"])
-@pytest.mark.parametrize("path", ["separate", "fused"])
+@pytest.mark.parametrize("path", ["separate", "fused", "fused2"])
 @pytest.mark.parametrize("shape", [(1000, 117, 2, 7), (77, 33, 3, 5), (1, 8, 1, 1), (130, 250, 1, 17)])
 def test_ragged_shapes_and_strides(dev, mode, path, shape):
     C, NL, ns, nz = shape
@@ -94,7 +95,8 @@ def test_ragged_shapes_and_strides(dev, mode, path, shape):
     g = synth.make_grid(NL, ns, nz)
     S = g.n_grains
     J, m = _inputs(g, C, 123 + C, dev, ldj=NL + 5)
-    plan = dust.Plan(g, mode)
+    plan = dust.Plan(g, mode, fused_kernels=2 if path == "fused2" else 1)
+    path = "fused" if path == "fused2" else path
     Tbuf = torch.full((C, S + 3), -3.0, dtype=torch.float32, device=dev)
     Lbuf = torch.full((C, NL + 7), -5.0, dtype=torch.float32, device=dev)
     T, L = Tbuf[:, :S], Lbuf[:, :NL]
