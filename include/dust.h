@@ -65,7 +65,8 @@ typedef enum {
     DUST_PLAIN_FP32 = 0,
     /* Mixed precision: heating on BF16 MFMA with hi+lo split operands and
        FP32 accumulation; T from an FP64 table of ln P(ln T) per grain with
-       an FP64 Newton polish on its cubic Hermite interpolant; FP32 emission. */
+       an FP64 Newton polish on its piecewise-cubic interpolant; FP32
+       emission. */
     DUST_MIXED = 1
 } dust_mode;
 
@@ -150,11 +151,18 @@ dust_status dust_run_fused(dust_plan* plan, int64_t n_cells,
 
 /* Many independent grids in one persistent launch.  A batch binds plans and
  * buffers once (host arrays of length n_grids; m_dust[g] may be NULL), builds
- * the work list of (grid, cell tile) items ordered by cost, picks tile shapes
- * with the autotuner when `autotune` is non-zero (timing candidate launches on
- * the bound buffers, which it overwrites) and records one HIP graph.
+ * the work list of (grid, cell tile) items ordered by cost and records one HIP
+ * graph.  Flags:
+ *   DUST_BATCH_AUTOTUNE       pick the tile shape (cells per tile, resident
+ *                             workgroups per CU) by timing candidate launches
+ *                             on the bound buffers, which it overwrites;
+ *   DUST_BATCH_REFRESH_PLANS  the graph first re-derives every plan's tables
+ *                             (dust_plan_prepare), so one replay is the whole
+ *                             path for every grid.
  * All plans must be DUST_MIXED plans of the current device. */
 typedef struct dust_batch dust_batch;
+
+enum { DUST_BATCH_AUTOTUNE = 1, DUST_BATCH_REFRESH_PLANS = 2 };
 
 dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids,
                               const int64_t* n_cells,
@@ -162,7 +170,7 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids,
                               const float* const* m_dust,
                               float* const* T, const int64_t* ldt,
                               float* const* L, const int64_t* ldl,
-                              dust_counters* counters, int32_t autotune,
+                              dust_counters* counters, int32_t flags,
                               dust_batch** out);
 
 /* Replay the batch's graph on `stream` (allocates nothing). */

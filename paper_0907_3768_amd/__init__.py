@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libdust.so")
 
 DUST_OK, DUST_EINVAL, DUST_EUNSUPPORTED, DUST_ENOMEM, DUST_EDEVICE = 0, -1, -2, -3, -4
 PLAIN, MIXED = 0, 1
+BATCH_AUTOTUNE, BATCH_REFRESH_PLANS = 1, 2
 _MODES = {"plain": PLAIN, "mixed": MIXED, PLAIN: PLAIN, MIXED: MIXED}
 
 _vp = ctypes.c_void_p
@@ -216,7 +217,8 @@ class Plan:
 class Batch:
     """Many grids in one persistent launch recorded in a HIP graph (dust_batch)."""
 
-    def __init__(self, plans: Sequence[Plan], J, m_dust, T, L, counters=None, autotune=True):
+    def __init__(self, plans: Sequence[Plan], J, m_dust, T, L, counters=None, autotune=True,
+                 refresh_plans=False):
         n = len(plans)
         arr = lambda typ, vals: (typ * n)(*vals)
         self._plans = list(plans)
@@ -238,7 +240,9 @@ class Batch:
                                        ctypes.cast(a[4], _vp), ctypes.cast(a[5], _vp),
                                        ctypes.cast(a[6], _vp), ctypes.cast(a[7], _vp),
                                        ctypes.cast(a[8], _vp), _ptr(counters),
-                                       1 if autotune else 0, ctypes.byref(h)))
+                                       (BATCH_AUTOTUNE if autotune else 0) |
+                                       (BATCH_REFRESH_PLANS if refresh_plans else 0),
+                                       ctypes.byref(h)))
         self._h = h
 
     def launch(self, stream=None):

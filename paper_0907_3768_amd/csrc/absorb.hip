@@ -48,15 +48,12 @@ hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj,
 hipError_t launch_absorb(const PlanView& v, int64_t C, const float* J, int64_t ldj, float* H,
                          int64_t ldh, hipStream_t st) {
     if (C == 0) return hipSuccess;
-    const int ntw = (v.Sp / 16 + 3) / 4;  // grain tiles per wave
+    const int ntw = (v.Sp / 16 + 3) / 4;  // grain tiles per wave in one pass
     if (ntw <= 1) return launch_ntw<1>(v, C, J, ldj, H, ldh, st);
     if (ntw <= 2) return launch_ntw<2>(v, C, J, ldj, H, ldh, st);
     if (ntw <= 3) return launch_ntw<3>(v, C, J, ldj, H, ldh, st);
     if (ntw <= 4) return launch_ntw<4>(v, C, J, ldj, H, ldh, st);
-    if (ntw <= 6) return launch_ntw<6>(v, C, J, ldj, H, ldh, st);
-    if (ntw <= 8) return launch_ntw<8>(v, C, J, ldj, H, ldh, st);
-    if (ntw <= 12) return launch_ntw<12>(v, C, J, ldj, H, ldh, st);
-    return launch_ntw<16>(v, C, J, ldj, H, ldh, st);
+    return launch_ntw<4>(v, C, J, ldj, H, ldh, st);  // several passes
 }
 
 }  // namespace dust

@@ -1,16 +1,22 @@
 // Many independent grids in one persistent launch.
 //
 // A batch binds (plan, buffers) per grid and a work list of (grid, cell tile)
-// items, heaviest tiles first (cost of a tile ~ NL x S of its grid).  Each
-// persistent workgroup takes the next item from a device counter, runs the
-// fused absorb -> solve -> emit body for that tile with the grid's tables,
-// and repeats until the list is exhausted.  Every workgroup reaches the exit
-// test after at most (items + 1) counter reads, so the grid always drains.
+// items, heaviest tiles first (cost of a tile ~ NL x S of its grid).  Two
+// launch forms run the fused absorb -> solve -> emit body on each item:
+//  * persistent: a fixed number of workgroups per CU; each takes the next item
+//    from a device counter and repeats until the list is exhausted (every
+//    workgroup reaches the exit test after at most items + 1 counter reads,
+//    so the grid always drains);
+//  * one workgroup per item, in list order (the hardware dispatcher is the
+//    queue).
 //
-// Tile shapes (cells per tile) and the number of resident workgroups per CU
-// are chosen by timing candidates on the bound buffers (autotuner); the
-// chosen launch (counter reset + persistent kernel) is recorded once into a
-// HIP graph and replayed by dust_batch_launch.
+// The form, the cells per tile and the grain tiles per heating pass are
+// chosen by timing candidates on the bound buffers (autotuner); the chosen
+// launch (with the counter reset, and optionally every plan's refresh) is
+// recorded once into a HIP graph and replayed by dust_batch_launch.
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -49,9 +55,13 @@ __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__
     for (;;) {
         if (threadIdx.x == 0) sItem = (int)atomicAdd(counter, 1u);
         __syncthreads();
-        const int it = sItem;
+        // Uniform across the block: keep the item and the grid descriptor in
+        // scalar registers (scalar loads) rather than in every lane.
+        const int it = __builtin_amdgcn_readfirstlane(sItem);
         if (it >= n_items) break;
-        const int2 w = items[it];
+        const int gx = __builtin_amdgcn_readfirstlane(items[it].x);
+        const int ty = __builtin_amdgcn_readfirstlane(items[it].y);
+        const int2 w = make_int2(gx, ty);
         const GridArgs& g = grids[w.x];
         fused_tile<DUST_MIXED, TC, NTW>(g.v, (int64_t)w.y * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L, g.ldl,
                             cnt, sTile);
@@ -59,9 +69,31 @@ __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__
     }
 }
 
+// One workgroup per work item (the hardware dispatcher hands items out in
+// list order, heaviest first).  Same tile body as the persistent kernel but
+// without its loop, which on gfx950 costs the persistent form a lot of
+// registers (values the compiler keeps live across items).
+template <int TC, int NTW>
+__global__ __launch_bounds__(256) void batch_item_kernel(const GridArgs* __restrict__ grids,
+                                                         const int2* __restrict__ items,
+                                                         int n_items, unsigned int* counter,
+                                                         dust_counters* cnt) {
+    extern __shared__ float sTile[];  // fused_lds_bytes(TC, Sp max)
+    const int it = blockIdx.x;
+    if (it >= n_items) return;
+    const int gx = __builtin_amdgcn_readfirstlane(items[it].x);
+    const int ty = __builtin_amdgcn_readfirstlane(items[it].y);
+    const GridArgs& g = grids[gx];
+    fused_tile<DUST_MIXED, TC, NTW>(g.v, (int64_t)ty * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L,
+                                    g.ldl, cnt, sTile);
+    (void)counter;
+}
+
 struct Candidate {
     int tc;        // cells per tile
-    int per_cu;    // resident workgroups per CU
+    int per_cu;    // resident workgroups per CU of the persistent kernel;
+                   // 0 = one workgroup per item
+    int ntw;       // grain tiles per wave in one pass of the heating
 };
 
 using KernelFn = void (*)(const GridArgs*, const int2*, int, unsigned int*, dust_counters*);
@@ -70,13 +102,19 @@ template <int TC>
 KernelFn pick_kernel(int ntw) {
     if (ntw <= 1) return batch_kernel<TC, 1>;
     if (ntw <= 2) return batch_kernel<TC, 2>;
-    if (ntw <= 4) return batch_kernel<TC, 4>;
-    if (ntw <= 8) return batch_kernel<TC, 8>;
-    return batch_kernel<TC, 16>;
+    return batch_kernel<TC, 4>;  // larger grain sets take several passes
 }
 
-KernelFn kernel_for(int tc, int ntw) {
-    return tc == 32 ? pick_kernel<32>(ntw) : pick_kernel<16>(ntw);
+template <int TC>
+KernelFn pick_item_kernel(int ntw) {
+    if (ntw <= 1) return batch_item_kernel<TC, 1>;
+    if (ntw <= 2) return batch_item_kernel<TC, 2>;
+    return batch_item_kernel<TC, 4>;
+}
+
+KernelFn kernel_for(int tc, int ntw, bool persistent) {
+    if (persistent) return tc == 32 ? pick_kernel<32>(ntw) : pick_kernel<16>(ntw);
+    return tc == 32 ? pick_item_kernel<32>(ntw) : pick_item_kernel<16>(ntw);
 }
 
 // Autotuner cache: the best candidate per (max-S bucket, mean-NL bucket,
@@ -91,7 +129,6 @@ struct dust_batch {
     int device;
     int n_grids;
     int sp_max;
-    int ntw;
     dust::Candidate cand;
     int64_t n_items_16, n_items_32;
     dust::GridArgs* d_grids;
@@ -110,12 +147,16 @@ namespace {
 hipError_t enqueue(const dust_batch* b, const Candidate& c, hipStream_t st) {
     const int2* items = c.tc == 32 ? b->d_items32 : b->d_items16;
     const int n_items = (int)(c.tc == 32 ? b->n_items_32 : b->n_items_16);
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int blocks = std::max(1, std::min(n_items, b->n_cu * c.per_cu));
+    const bool persistent = c.per_cu > 0;
+    if (persistent) {
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int blocks = persistent ? std::max(1, std::min(n_items, b->n_cu * c.per_cu))
+                                  : std::max(1, n_items);
     const size_t lds = fused_lds_bytes(c.tc, b->sp_max);
-    hipLaunchKernelGGL(kernel_for(c.tc, b->ntw), dim3(blocks), dim3(256), lds, st,
+    hipLaunchKernelGGL(kernel_for(c.tc, c.ntw, persistent), dim3(blocks), dim3(256), lds, st,
                        (const GridArgs*)b->d_grids, items, n_items, b->d_counter, b->counters);
     return hipGetLastError();
 }
@@ -156,7 +197,9 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
                               const float* const* J, const int64_t* ldj,
                               const float* const* m_dust, float* const* T, const int64_t* ldt,
                               float* const* L, const int64_t* ldl, dust_counters* counters,
-                              int32_t autotune, dust_batch** out) {
+                              int32_t flags, dust_batch** out) {
+    const bool autotune = (flags & DUST_BATCH_AUTOTUNE) != 0;
+    const bool refresh = (flags & DUST_BATCH_REFRESH_PLANS) != 0;
     if (!out) return set_error(DUST_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_grids < 1) return set_error(DUST_EINVAL, "n_grids must be >= 1");
@@ -164,6 +207,8 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
         return set_error(DUST_EINVAL, "a per-grid array is NULL");
     if (counters && ((uintptr_t)counters & 7u))
         return set_error(DUST_EINVAL, "counters must be 8-byte aligned");
+    if (flags & ~(DUST_BATCH_AUTOTUNE | DUST_BATCH_REFRESH_PLANS))
+        return set_error(DUST_EINVAL, "unknown batch flags");
     std::vector<GridArgs> args(n_grids);
     std::vector<int64_t> C(n_grids);
     std::vector<double> cost(n_grids);
@@ -207,7 +252,6 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     b->device = dev;
     b->n_grids = n_grids;
     b->sp_max = sp_max;
-    b->ntw = (sp_max / 16 + 3) / 4;
     b->n_cu = prop.multiProcessorCount;
     b->counters = counters;
     std::vector<int2> it16 = build_items(C, cost, 16), it32 = build_items(C, cost, 32);
@@ -233,13 +277,18 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     // Candidate tile shapes.  32-cell tiles need twice the LDS per workgroup;
     // a workgroup may hold at most 64 KiB and a CU 160 KiB.
     std::vector<Candidate> cands;
+    const int ntw_need = (sp_max / 16 + 3) / 4;
     for (int tc : {16, 32})
-        for (int per_cu : {1, 2, 4, 8}) {
-            const size_t lds = fused_lds_bytes(tc, sp_max);
-            if (lds <= (size_t)max_lds && lds * per_cu <= 160u * 1024u)
-                cands.push_back(Candidate{tc, per_cu});
+        for (int ntw : {1, 2, 4}) {
+            if (ntw > 1 && ntw / 2 >= ntw_need) continue;  // no more depth than needed
+            for (int per_cu : {0, 2, 4}) {
+                const size_t lds = fused_lds_bytes(tc, sp_max);
+                if (lds <= (size_t)max_lds && lds * std::max(per_cu, 1) <= 160u * 1024u)
+                    cands.push_back(Candidate{tc, per_cu, ntw});
+            }
         }
-    Candidate best{16, 2};
+    Candidate best{16, 0, ntw_need < 2 ? ntw_need : 2};
+    const bool verbose = getenv("DUST_LOG") != nullptr;
     if (autotune && !cands.empty()) {
         double mean_nl = 0.0;
         for (int g = 0; g < n_grids; ++g) mean_nl += plans[g]->NL;
@@ -271,6 +320,9 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
                     (void)hipEventElapsedTime(&ms, e0, e1);
                     total += ms;
                 }
+                if (verbose)
+                    fprintf(stderr, "dust batch autotune: tc=%d ntw=%d per_cu=%d  %.3f ms%s\n",
+                            c.tc, c.ntw, c.per_cu, total / 2, ok ? "" : " (failed)");
                 if (ok && total < best_ms) { best_ms = total; best = c; }
             }
             (void)hipStreamSynchronize(st);
@@ -288,7 +340,16 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     if ((e = hipStreamCreate(&cs)) != hipSuccess) { free_batch(b); return hip_error(e, "hipStreamCreate"); }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = enqueue(b, best, cs);
+        hipError_t le = hipSuccess;
+        if (refresh) {
+            std::vector<const dust_plan*> seen;
+            for (int g = 0; g < n_grids && le == hipSuccess; ++g) {
+                if (std::find(seen.begin(), seen.end(), plans[g]) != seen.end()) continue;
+                seen.push_back(plans[g]);
+                le = launch_prepare(plans[g], cs);
+            }
+        }
+        if (le == hipSuccess) le = enqueue(b, best, cs);
         e = hipStreamEndCapture(cs, &b->graph);
         if (e == hipSuccess && le != hipSuccess) e = le;
     }

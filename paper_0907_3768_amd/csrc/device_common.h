@@ -276,38 +276,29 @@ __device__ inline int table_lookup_f64(const PlanView& v, int s, double hs, floa
     return 0;
 }
 
-// Mixed solve of one pair per lane.  Every lane of the wave must call it
-// (inactive lanes pass active = false); pairs outside the table are then
-// solved exactly one after another by the whole wave.
-__device__ inline float wave_solve_mixed(const PlanView& v, bool active, int s, double hs,
-                                         dust_counters* cnt) {
-    float T = 0.0f;
+// Exact FP64 solve of one pending pair (status 1, 2 or 3 from
+// table_lookup_f64) by the whole wave: every lane calls it with the same
+// arguments and receives T.  Counts the pair as out of table.
+__device__ inline float wave_solve_pending(const PlanView& v, int s, double hs,
+                                           dust_counters* cnt) {
+    float T;
     double lnT0 = 0.0;
-    const int status = active ? table_lookup_f64(v, s, hs, &T, &lnT0, cnt) : 0;
-    uint64_t pend = __ballot(status != 0);
-    const int lane = threadIdx.x & 63;
+    const int st = table_lookup_f64(v, s, hs, &T, &lnT0, nullptr);
+    if (st == 0) return T;  // cannot happen for a pending pair; harmless
     const double lnTmax = v.lnTmin + (v.N - 1) * v.hstep;
-    while (pend) {
-        const int src = __ffsll((unsigned long long)pend) - 1;
-        pend &= pend - 1;
-        const int ss = __shfl(s, src, 64);
-        const double hh = __shfl(hs, src, 64);
-        const int st = __shfl(status, src, 64);
-        const double g = __shfl(lnT0, src, 64);
-        const double lo = (st == 2) ? lnTmax : -6.907755278982137;  // ln 1e-3
-        const double hi = (st == 1) ? v.lnTmin : 16.11809565095832;  // ln 1e7
-        bool ok = false;
-        const double lnT = wave_solve_exact_f64(v, ss, hh, lo, hi, g, &ok);
-        if (lane == src) {
-            T = (float)exp(lnT);
-            if (cnt) {
-                count(&cnt->n_out_of_table);
-                if (!ok) count(&cnt->n_unconverged);
-            }
-        }
+    const double lo = (st == 2) ? lnTmax : -6.907755278982137;  // ln 1e-3
+    const double hi = (st == 1) ? v.lnTmin : 16.11809565095832;  // ln 1e7
+    bool ok = false;
+    const double lnT = wave_solve_exact_f64(v, s, hs, lo, hi, lnT0, &ok);
+    if (cnt && (threadIdx.x & 63) == 0) {
+        count(&cnt->n_out_of_table);
+        if (!ok) count(&cnt->n_unconverged);
     }
-    return T;
+    return (float)exp(lnT);
 }
+
+// Capacity of a block's LDS list of pending pairs.
+constexpr int PENDING_CAP = 256;
 
 // ---------------------------------------------------------------------------
 // Emission of TC cells at one wavelength (Eqs. 9-10, Section 4.4).

@@ -26,18 +26,19 @@ __global__ __launch_bounds__(256) void absorb_solve_kernel(PlanView v, int64_t C
                                                           const float* __restrict__ J,
                                                           int64_t ldj, float* __restrict__ T,
                                                           int64_t ldt, dust_counters* cnt) {
-    extern __shared__ float lds[];  // sH [16][Sp], then the J staging buffers
+    extern __shared__ float lds[];  // sH [16][Sp], J staging, pending list
     char* sStage = reinterpret_cast<char*>(lds + FUSED_TC * v.Sp);
     const int64_t c0 = (int64_t)blockIdx.x * FUSED_TC;
     fused_absorb<MODE, NTW>(v, c0, C, J, ldj, lds, sStage);
     __syncthreads();
-    fused_solve<MODE, FUSED_TC>(v, c0, C, T, ldt, cnt, lds);
+    fused_solve<MODE, FUSED_TC>(v, c0, C, T, ldt, cnt, lds,
+                                reinterpret_cast<int*>(sStage + STAGE_BYTES));
 }
 
 template <int NTW>
 hipError_t launch_as_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj, float* T,
                          int64_t ldt, dust_counters* cnt, hipStream_t st) {
-    const size_t lds = sizeof(float) * FUSED_TC * v.Sp + STAGE_BYTES;
+    const size_t lds = sizeof(float) * FUSED_TC * v.Sp + STAGE_BYTES + SOLVE_LDS_BYTES;
     const dim3 grid((unsigned)((C + FUSED_TC - 1) / FUSED_TC));
     if (v.mode == DUST_MIXED)
         hipLaunchKernelGGL((absorb_solve_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v,
@@ -69,15 +70,12 @@ hipError_t launch_fused(const PlanView& v, int64_t C, const float* J, int64_t ld
                         float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
                         hipStream_t st) {
     if (C == 0) return hipSuccess;
-    const int ntw = (v.Sp / 16 + 3) / 4;  // grain tiles per wave
+    const int ntw = (v.Sp / 16 + 3) / 4;  // grain tiles per wave in one pass
     if (ntw <= 1) return launch_ntw<1>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
     if (ntw <= 2) return launch_ntw<2>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
     if (ntw <= 3) return launch_ntw<3>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
     if (ntw <= 4) return launch_ntw<4>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
-    if (ntw <= 6) return launch_ntw<6>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
-    if (ntw <= 8) return launch_ntw<8>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
-    if (ntw <= 12) return launch_ntw<12>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
-    return launch_ntw<16>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    return launch_ntw<4>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);  // several passes
 }
 
 hipError_t launch_absorb_solve(const PlanView& v, int64_t C, const float* J, int64_t ldj,
@@ -88,10 +86,7 @@ hipError_t launch_absorb_solve(const PlanView& v, int64_t C, const float* J, int
     if (ntw <= 2) return launch_as_ntw<2>(v, C, J, ldj, T, ldt, cnt, st);
     if (ntw <= 3) return launch_as_ntw<3>(v, C, J, ldj, T, ldt, cnt, st);
     if (ntw <= 4) return launch_as_ntw<4>(v, C, J, ldj, T, ldt, cnt, st);
-    if (ntw <= 6) return launch_as_ntw<6>(v, C, J, ldj, T, ldt, cnt, st);
-    if (ntw <= 8) return launch_as_ntw<8>(v, C, J, ldj, T, ldt, cnt, st);
-    if (ntw <= 12) return launch_as_ntw<12>(v, C, J, ldj, T, ldt, cnt, st);
-    return launch_as_ntw<16>(v, C, J, ldj, T, ldt, cnt, st);
+    return launch_as_ntw<4>(v, C, J, ldj, T, ldt, cnt, st);  // several passes
 }
 
 }  // namespace dust

@@ -23,8 +23,9 @@ constexpr int STAGE_BYTES = 2 * STAGE_BUF_BYTES;
 // Per K-step of 32 wavelengths the block loads the 16 x 32 chunk of J with
 // coalesced loads (thread t: row t/16, columns 2(t mod 16) and +1), splits it
 // (mixed: bf16 hi + lo) into LDS, and each wave multiplies it with its grain
-// tiles w, w+4, ... (NTW of them).  The next chunk of J is loaded into
-// registers while the current MFMAs run.
+// tiles w, w+4, ... (NTW of them per pass; grids with more than 4 NTW tiles
+// take several passes).  The next chunk of J is loaded into registers while
+// the current MFMAs run.
 //
 // K-order: lane (row = lane mod 16, q = lane / 16) supplies wavelengths
 // k0 + 8q .. k0 + 8q + 7 to both operands -- one 16x16x32 bf16 MFMA, or eight
@@ -44,10 +45,6 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
     const int lrow = tid >> 4, lcol = (tid & 15) * 2;
     const bool lrow_ok = c0 + lrow < C;
     const float* jl = J + (lrow_ok ? c0 + lrow : 0) * ldj;
-
-    f32x4 acc[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     auto load_j = [&](int k0, float& x0, float& x1) {
         const int k = k0 + lcol;
@@ -72,6 +69,11 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
     };
 
     const int nsteps = (v.NL + 31) / 32;
+    // Grain tiles in groups of 4 NTW (one pass over J each).
+    for (int tg = 0; tg < tiles; tg += 4 * NTW) {
+    f32x4 acc[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     float x0, x1;
     load_j(0, x0, x1);
     store_j(0, x0, x1);
@@ -87,7 +89,7 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
                 b + 16 * STAGE_ROW_BF16 + row * STAGE_ROW_BF16 + kq * 8);
 #pragma unroll
             for (int t = 0; t < NTW; ++t) {
-                const int tile = wave + 4 * t;
+                const int tile = tg + wave + 4 * t;
                 if (tile < tiles) {
                     const int64_t o = (int64_t)(tile * 16 + row) * v.NLp + k0 + kq * 8;
                     const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(v.khi + o);
@@ -104,7 +106,7 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
             const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
             for (int t = 0; t < NTW; ++t) {
-                const int tile = wave + 4 * t;
+                const int tile = tg + wave + 4 * t;
                 if (tile < tiles) {
                     const float* kr = v.kf + (int64_t)(tile * 16 + row) * v.NLp + k0 + kq * 8;
                     const float4 b0 = *reinterpret_cast<const float4*>(kr);
@@ -121,39 +123,90 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
     }
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
-        const int tile = wave + 4 * t;
+        const int tile = tg + wave + 4 * t;
         if (tile < tiles) {
             const int s = tile * 16 + row;
 #pragma unroll
             for (int r = 0; r < 4; ++r) sH[(kq * 4 + r) * v.Sp + s] = acc[t][r];
         }
     }
+    }  // tile groups
 }
 
 // Phases 2 and 3 on a tile whose scaled heating sits in sH: solve every pair
 // (T to device memory, 1/T back into sH), then emit the tile's SEDs.  The
 // group minima of 1/T follow sH in LDS (see emit_accumulate).
+// LDS used by the solve phase for its list of pending pairs.
+constexpr int SOLVE_LDS_BYTES = (PENDING_CAP + 4) * (int)sizeof(int);
+
+// Phase 2: solve every pair of the tile from sH (scaled heating), write T and
+// leave 1/T in sH.  Pairs outside the mixed table are marked by a negative
+// sH (-H'), listed in LDS and solved exactly by the block's waves in turn;
+// the list is rebuilt until no mark is left.
 template <int MODE, int TC>
 __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64_t C,
                                             float* __restrict__ T, int64_t ldt,
-                                            dust_counters* cnt, float* sH) {
+                                            dust_counters* cnt, float* sH, int* sSolve) {
     const int n = TC * v.Sp;
-    // Same trip count for every lane: the mixed solve works wave-wide.
-    for (int base = 0; base < n; base += blockDim.x) {
-        const int i = base + threadIdx.x;
+    int* sCount = sSolve;
+    int* sList = sSolve + 4;
+    if constexpr (MODE == DUST_MIXED) {
+        if (threadIdx.x == 0) *sCount = 0;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int cc = i / v.Sp, s = i - cc * v.Sp;
         const int64_t c = c0 + cc;
-        const bool pair = i < n && s < v.S && c < C;
-        float t = 0.0f;
-        if constexpr (MODE == DUST_MIXED) {
-            t = wave_solve_mixed(v, pair, pair ? s : 0, pair ? (double)sH[i] : 0.0, cnt);
-        } else {
-            if (pair)
+        const bool pair = s < v.S && c < C;
+        float inv = __builtin_inff();
+        if (pair) {
+            float t;
+            if constexpr (MODE == DUST_MIXED) {
+                const float h = sH[i];
+                double lnT0;
+                if (table_lookup_f64(v, s, (double)h, &t, &lnT0, cnt) != 0) {
+                    const int k = atomicAdd(sCount, 1);
+                    if (k < PENDING_CAP) sList[k] = i;
+                    sH[i] = -h;  // pending: solved below
+                    continue;
+                }
+            } else {
                 t = solve_newton_f32(v.kb + (int64_t)s * v.NLp, v.nu, v.NL, sH[i], v.gs[s],
                                      v.tol, v.maxit, cnt);
+            }
+            T[c * ldt + s] = t;
+            inv = inv_temperature(t);
         }
-        if (pair) T[c * ldt + s] = t;
-        if (i < n) sH[i] = pair ? inv_temperature(t) : __builtin_inff();
+        sH[i] = inv;
+    }
+    if constexpr (MODE == DUST_MIXED) {
+        __syncthreads();
+        for (;;) {
+            const int total = *sCount;
+            if (total == 0) break;  // uniform: read after a barrier
+            const int listed = total < PENDING_CAP ? total : PENDING_CAP;
+            for (int e = threadIdx.x >> 6; e < listed; e += blockDim.x >> 6) {
+                const int i = sList[e];
+                const int cc = i / v.Sp, s = i - cc * v.Sp;
+                const float t = wave_solve_pending(v, s, -(double)sH[i], cnt);
+                if ((threadIdx.x & 63) == 0) {
+                    T[(c0 + cc) * ldt + s] = t;
+                    sH[i] = inv_temperature(t);
+                }
+            }
+            __syncthreads();
+            if (total <= PENDING_CAP) break;
+            // the list overflowed: collect the pairs still marked
+            if (threadIdx.x == 0) *sCount = 0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                if (sH[i] < 0.0f) {
+                    const int k = atomicAdd(sCount, 1);
+                    if (k < PENDING_CAP) sList[k] = i;
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -164,7 +217,9 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
                                                  float* __restrict__ L, int64_t ldl,
                                                  dust_counters* cnt, float* sH) {
     const int n = TC * v.Sp;
-    fused_solve<MODE, TC>(v, c0, C, T, ldt, cnt, sH);
+    fused_solve<MODE, TC>(v, c0, C, T, ldt, cnt, sH,
+                          reinterpret_cast<int*>(reinterpret_cast<char*>(sH) +
+                                                 emit_lds_bytes(TC, v.Sp) + STAGE_BYTES));
     __syncthreads();
     uint32_t* sChunk = reinterpret_cast<uint32_t*>(sH + n);
     fill_chunk_min<TC>(sH, sChunk, v.Sp);
@@ -191,9 +246,10 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
 }
 
 // LDS bytes of a fused tile of TC cells: the emission tile (whose first
-// TC x Sp floats hold H' and then 1/T) plus the J staging buffers.
+// TC x Sp floats hold H' and then 1/T), the J staging buffers and the solve
+// phase's pending list.
 __host__ __device__ constexpr size_t fused_lds_bytes(int TC, int Sp) {
-    return emit_lds_bytes(TC, Sp) + STAGE_BYTES;
+    return emit_lds_bytes(TC, Sp) + STAGE_BYTES + SOLVE_LDS_BYTES;
 }
 
 // One tile of TC cells (TC a multiple of 16) starting at cell c0; lds holds

@@ -77,6 +77,7 @@ struct dust_plan {
     float *d_nu, *d_hscale, *d_hinv, *d_gs, *d_kf, *d_kb, *d_em;
     __bf16 *d_khi, *d_klo;
     double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv, *d_fwd, *d_texp;
+    double* d_F;  // [N][NL] Planck factors of the table temperatures (mixed)
     double2 *d_inv, *d_lntab;
     dust::PlanView view;
 };

@@ -7,7 +7,8 @@
 //        exponent table nu = -c2 log2(e) / lam.
 //  ltab  (mixed mode): per grain, y_k = ln P'(T_k) at log-spaced T_k, in
 //        FP64, with P'(T) = sum_l K'_l B(lam_l, T) the right side of Eq. 7 in
-//        the plan's scaled units.
+//        the plan's scaled units -- as an FP64 matrix product of the grains'
+//        Planck weights with the Planck factors of the table temperatures.
 //  inv   (mixed mode): the inverse function ln T(y) and its derivative at
 //        uniform steps of y, from Newton on the forward table's piecewise
 //        cubic, so that a lookup starts next to its root.
@@ -55,18 +56,40 @@ __global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __r
     }
 }
 
-// One thread per (grain, table point).  Per term: one multiply, e^x - 1 and
-// one division; B = c1 lam^-5 / (e^x - 1).
-__global__ __launch_bounds__(256) void ltab_kernel(PlanView v, double* fwd) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
-    if (k >= v.N) return;
+// The table is a matrix product:  P'[s,k] = sum_l W[s,l] F[k,l]  with
+// W = K' c1 lam^-5 (per grain) and F[k,l] = 1 / (exp(c2 / (lam_l T_k)) - 1)
+// (per table temperature, the same for every grain).  F takes N x NL
+// exponentials once; the product is FP64 FMA work.
+
+// F[k][l], one thread per element.
+__global__ __launch_bounds__(256) void planck_factor_kernel(PlanView v, double* F) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (l >= v.NL) return;
     const double invT = exp(-(v.lnTmin + k * v.hstep));
-    const double* kdb = v.kdb + (int64_t)s * v.NL;
-    double P = 0.0;
-    for (int l = 0; l < v.NL; ++l)
-        P += kdb[l] / expm1_pos(v.c2l[l] * invT);  // 0 once e^x overflows
-    fwd[(int64_t)s * v.N + k] = log(P);
+    F[(int64_t)k * v.NL + l] = 1.0 / expm1_pos(v.c2l[l] * invT);  // 0 once e^x overflows
+}
+
+// y[s][k] = ln sum_l W[s][l] F[k][l]: FP64 GEMM, 16 x 16 output tile per
+// 256-thread block, 16-wide chunks of l staged in LDS.
+__global__ __launch_bounds__(256) void ltab_gemm_kernel(PlanView v, const double* __restrict__ F,
+                                                        double* fwd) {
+    __shared__ double sW[16][17];
+    __shared__ double sF[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int k0 = blockIdx.x * 16, s0 = blockIdx.y * 16;
+    const int k = k0 + tx, s = s0 + ty;
+    double acc = 0.0;
+    for (int l0 = 0; l0 < v.NL; l0 += 16) {
+        const int ls = l0 + tx;
+        sW[ty][tx] = (s0 + ty < v.S && ls < v.NL) ? v.kdb[(int64_t)(s0 + ty) * v.NL + ls] : 0.0;
+        sF[ty][tx] = (k0 + ty < v.N && ls < v.NL) ? F[(int64_t)(k0 + ty) * v.NL + ls] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc = fma(sW[ty][i], sF[tx][i], acc);
+        __syncthreads();
+    }
+    if (s < v.S && k < v.N) fwd[(int64_t)s * v.N + k] = log(acc);
 }
 
 // One thread per (grain, inverse node): ln T at y_j = ylo + j dy, by Newton
@@ -117,8 +140,12 @@ hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
                        p->d_em, p->d_kdb, p->d_c2l);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || v.mode != DUST_MIXED) return e;
-    dim3 g2((v.N + 255) / 256, v.S);
-    hipLaunchKernelGGL(ltab_kernel, g2, dim3(256), 0, st, v, p->d_fwd);
+    dim3 gf((v.NL + 255) / 256, v.N);
+    hipLaunchKernelGGL(planck_factor_kernel, gf, dim3(256), 0, st, v, p->d_F);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g2((v.N + 15) / 16, (v.S + 15) / 16);
+    hipLaunchKernelGGL(ltab_gemm_kernel, g2, dim3(256), 0, st, v, (const double*)p->d_F, p->d_fwd);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g3((v.M + 255) / 256, v.S);

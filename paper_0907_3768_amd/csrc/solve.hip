@@ -22,18 +22,40 @@ __global__ __launch_bounds__(256) void solve_plain_kernel(PlanView v, int64_t C,
                                       v.tol, v.maxit, cnt);
 }
 
-// One thread per (cell, grain) in row-major order: coalesced H and T.
+// One thread per (cell, grain) in row-major order: coalesced H and T.  Pairs
+// outside the table go to an LDS list and are then solved exactly by the
+// block's waves in turn (one pair per wave at a time, lanes over wavelength).
 __global__ __launch_bounds__(256) void solve_mixed_kernel(PlanView v, int64_t C,
                                                           const float* __restrict__ H,
                                                           int64_t ldh, float* __restrict__ T,
                                                           int64_t ldt, dust_counters* cnt) {
+    __shared__ int sCount;
+    __shared__ int sList[256];
+    if (threadIdx.x == 0) sCount = 0;
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool active = i < C * v.S;  // every lane stays for the wave-wide fallback
+    const bool active = i < C * v.S;
     const int64_t c = active ? i / v.S : 0;
     const int s = active ? (int)(i - c * v.S) : 0;
     const double hs = active ? (double)H[c * ldh + s] * (double)v.hscale[s] : 0.0;
-    const float t = wave_solve_mixed(v, active, s, hs, cnt);
-    if (active) T[c * ldt + s] = t;
+    float t = 0.0f;
+    double lnT0;
+    if (active) {
+        if (table_lookup_f64(v, s, hs, &t, &lnT0, cnt) != 0)
+            sList[atomicAdd(&sCount, 1)] = threadIdx.x;
+        else
+            T[c * ldt + s] = t;
+    }
+    __syncthreads();
+    const int n = sCount;
+    for (int e = threadIdx.x >> 6; e < n; e += blockDim.x >> 6) {
+        const int64_t ip = (int64_t)blockIdx.x * 256 + sList[e];
+        const int64_t cp = ip / v.S;
+        const int sp = (int)(ip - cp * v.S);
+        const double hp = (double)H[cp * ldh + sp] * (double)v.hscale[sp];
+        const float tp = wave_solve_pending(v, sp, hp, cnt);
+        if ((threadIdx.x & 63) == 0) T[cp * ldt + sp] = tp;
+    }
 }
 
 }  // namespace

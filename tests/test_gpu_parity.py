@@ -303,7 +303,8 @@ def test_full_size_sampled(dev, name, mode):
 
 # --------------------------------------------------------------------------- batched persistent launch
 
-def test_batch_matches_oracle_and_replays(dev):
+@pytest.mark.parametrize("refresh", [False, True])
+def test_batch_matches_oracle_and_replays(dev, refresh):
     specs = synth.batch_specs(n_grids=12, scale=0.02)
     plans, Js, ms, Ts, Ls, grids, params = [], [], [], [], [], [], []
     for s in specs:
@@ -318,7 +319,7 @@ def test_batch_matches_oracle_and_replays(dev):
         Ls.append(torch.zeros((s.n_cells, g.n_lambda), dtype=torch.float32, device=dev))
     cnt = dust.new_counters(dev)
     say("batch: create (autotune + graph capture)")
-    b = dust.Batch(plans, Js, ms, Ts, Ls, counters=cnt, autotune=True)
+    b = dust.Batch(plans, Js, ms, Ts, Ls, counters=cnt, autotune=True, refresh_plans=refresh)
     say("batch info", b.info())
     ref = None
     for rep in range(3):
