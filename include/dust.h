@@ -149,11 +149,12 @@ dust_status dust_run_fused(dust_plan* plan, int64_t n_cells,
                            float* T, int64_t ldt, float* L, int64_t ldl,
                            dust_counters* counters, void* stream);
 
-/* Many independent grids in one persistent launch.  A batch binds plans and
+/* Many independent grids in one launch.  A batch binds plans and
  * buffers once (host arrays of length n_grids; m_dust[g] may be NULL), builds
  * the work list of (grid, cell tile) items ordered by cost and records one HIP
  * graph.  Flags:
- *   DUST_BATCH_AUTOTUNE       pick the tile shape (cells per tile, resident
+ *   DUST_BATCH_AUTOTUNE       pick the launch form (one workgroup per item,
+ *                             or a work queue) and the tile shape (cells per tile, resident
  *                             workgroups per CU) by timing candidate launches
  *                             on the bound buffers, which it overwrites;
  *   DUST_BATCH_REFRESH_PLANS  the graph first re-derives every plan's tables

@@ -6,13 +6,17 @@ no code, header, table or constant with the GPU path.
 
 The arithmetic lives in ``dust_ref.c`` (plain C, IEEE double precision, one
 function per equation of Section 4: Eq. 6 heating, Eq. 7 temperature root,
-Eqs. 9-10 emission, Eq. 11 initial guess).  This module builds that file with
-gcc and marshals numpy arrays to it.
+Eqs. 9-10 emission, Eq. 11 initial guess, and the production variant of the
+temperature step: linear interpolation in a table of the grain power).  This
+module builds that file with gcc, marshals numpy arrays to it, and adds the
+non-radiative heating term and the outer re-heating iteration (Section 2) as
+plain numpy around those calls.
 
 Every function is pinned by tests against what physics and mathematics fix
 (Stefan-Boltzmann, Wien displacement, grey and power-law grains in diluted
 blackbody fields, brute-force bisection, the SED energy identity, BLAS for
-the heating product).  The Eq. 11 guess is not pinned to any value (the
+the heating product, numpy's piecewise-linear interpolation for the table
+variant, closed forms for the extra heating and the re-heating series).  The Eq. 11 guess is not pinned to any value (the
 paper prints none for the grains used here); it only changes how many
 iterations the solve takes, never the root, and a test checks exactly that.
 """
@@ -67,6 +71,10 @@ def lib():
         L.dust_ref_temperature.argtypes = [_i64, _i32, _i32, _p, _p, _p, _p, _p, _p, _p]
         L.dust_ref_emission.restype = None
         L.dust_ref_emission.argtypes = [_i64, _i32, _i32, _p, _p, _p, _p, _p, _p]
+        L.dust_ref_table_build.restype = None
+        L.dust_ref_table_build.argtypes = [_i32, _i32, _p, _p, _p, _i32, _d, _d, _p]
+        L.dust_ref_table_temperature.restype = _i64
+        L.dust_ref_table_temperature.argtypes = [_i64, _i32, _i32, _d, _d, _p, _p, _p]
         L.dust_ref_get_threads.restype = ctypes.c_int
         L.dust_ref_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -143,12 +151,67 @@ def emission(T, lam, c_abs, weight, m_dust=None):
     return L
 
 
-def run(grid, J, m_dust=None, return_iters=False):
-    """The whole path on one grid: (H, T, L[, iters])."""
+def table_build(lam, dlam, c_abs, n_T=2000, t_min=3.0, t_max=1500.0):
+    """Production variant (Sections 2 and 5): P[S, n_T], the grain power of
+    Eq. 7 at n_T temperatures evenly spaced over [t_min, t_max]."""
+    lam, dlam, c_abs = _f64(lam), _f64(dlam), _f64(c_abs)
+    S, NL = c_abs.shape
+    P = np.empty((S, n_T), dtype=np.float64)
+    lib().dust_ref_table_build(NL, S, _ptr(lam), _ptr(dlam), _ptr(c_abs), int(n_T),
+                               float(t_min), float(t_max), _ptr(P))
+    return P
+
+
+def table_temperature(H, P, t_min=3.0, t_max=1500.0):
+    """T[C, S] by linear interpolation in the table P (see ``table_build``);
+    returns (T, number of pairs outside the table, which get the end T)."""
+    H, P = _f64(H), _f64(P)
+    C, S = H.shape
+    n_T = P.shape[1]
+    assert P.shape == (S, n_T) and n_T >= 2
+    T = np.empty((C, S), dtype=np.float64)
+    n = lib().dust_ref_table_temperature(C, S, n_T, float(t_min), float(t_max), _ptr(P),
+                                         _ptr(H), _ptr(T))
+    return T, int(n)
+
+
+def run(grid, J, m_dust=None, return_iters=False, Q=None, table=None):
+    """The whole path on one grid: (H, T, L[, iters]).
+
+    Q (optional, [C, S]) is heating from sources other than the radiation
+    field, added to H before the balance is solved (Section 2: the heating
+    need not be absorbed radiation); the returned H is the total.  ``table``
+    = (n_T, t_min, t_max) selects the production variant of the temperature
+    step (linear interpolation in a T table) instead of the exact root; iters
+    are then zero."""
     H = heating(J, grid.c_abs, grid.dlam)
-    T, it = temperature(H, grid.lam, grid.dlam, grid.c_abs, grid.size, return_iters=True)
+    if Q is not None:
+        H = H + _f64(Q)
+    if table is None:
+        T, it = temperature(H, grid.lam, grid.dlam, grid.c_abs, grid.size, return_iters=True)
+    else:
+        n_T, t_min, t_max = table
+        P = table_build(grid.lam, grid.dlam, grid.c_abs, n_T, t_min, t_max)
+        T, _ = table_temperature(H, P, t_min, t_max)
+        it = np.zeros(T.shape, dtype=np.int32)
     L = emission(T, grid.lam, grid.c_abs, grid.weight, m_dust)
     return (H, T, L, it) if return_iters else (H, T, L)
+
+
+def reheat(grid, J0, m_dust, coupling, n_passes, Q=None, table=None):
+    """Global iteration for dust that absorbs its own emission (Section 2):
+    pass 0 heats with J0; pass n with J_n = J0 + coupling[c] * L_{n-1}[c, l],
+    the stand-in for re-propagating the previous pass's emission.  Returns
+    the list of (H, T, L) of every pass."""
+    J0 = _f64(J0)
+    g = _f64(coupling)[:, None]
+    out = []
+    J = J0
+    for _ in range(n_passes):
+        H, T, L = run(grid, J, m_dust, Q=Q, table=table)
+        out.append((H, T, L))
+        J = J0 + g * L
+    return out
 
 
 def threads() -> int:

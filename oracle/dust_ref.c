@@ -177,6 +177,68 @@ void dust_ref_emission(int64_t n_cells, int32_t NL, int32_t S,
     }
 }
 
+/*
+ * The production variant of the temperature step (Sections 2 and 5): per
+ * grain, the power P_s(T_k) of Eq. 7 at n_T temperatures evenly spaced from
+ * t_min to t_max, T_k = t_min + k (t_max - t_min) / (n_T - 1).
+ */
+void dust_ref_table_build(int32_t NL, int32_t S, const double* lam,
+                          const double* dlam, const double* c_abs,
+                          int32_t n_T, double t_min, double t_max, double* P)
+{
+    const double step = (t_max - t_min) / (double)(n_T - 1);
+#pragma omp parallel for schedule(static)
+    for (int32_t s = 0; s < S; ++s)
+        for (int32_t k = 0; k < n_T; ++k)
+            P[(int64_t)s * n_T + k] =
+                dust_ref_grain_power(NL, lam, dlam, c_abs + (int64_t)s * NL,
+                                     t_min + k * step);
+}
+
+/*
+ * T(H) from the table by linear interpolation between the two table points
+ * whose powers bracket H: P_k <= H < P_{k+1} gives
+ *   T = T_k + (H - P_k) / (P_{k+1} - P_k) * (T_{k+1} - T_k).
+ * H = 0 gives 0; H < 0 or non-finite gives NaN.  H below the table gives
+ * t_min and H above it t_max; those pairs are counted (return value).
+ */
+int64_t dust_ref_table_temperature(int64_t n_cells, int32_t S, int32_t n_T,
+                                   double t_min, double t_max, const double* P,
+                                   const double* H, double* T)
+{
+    const double step = (t_max - t_min) / (double)(n_T - 1);
+    int64_t clamped = 0;
+#pragma omp parallel for schedule(static) reduction(+:clamped)
+    for (int64_t c = 0; c < n_cells; ++c) {
+        for (int32_t s = 0; s < S; ++s) {
+            const double h = H[c * S + s];
+            const double* row = P + (int64_t)s * n_T;
+            double t;
+            if (isnan(h) || isinf(h) || h < 0.0) {
+                t = NAN;
+            } else if (h == 0.0) {
+                t = 0.0;
+            } else if (h < row[0]) {
+                t = t_min;
+                ++clamped;
+            } else if (h >= row[n_T - 1]) {
+                t = t_max;
+                if (h > row[n_T - 1]) ++clamped;
+            } else {
+                int32_t lo = 0, hi = n_T - 1;   /* row[lo] <= h < row[hi] */
+                while (hi - lo > 1) {
+                    const int32_t mid = lo + (hi - lo) / 2;
+                    if (row[mid] <= h) lo = mid;
+                    else hi = mid;
+                }
+                t = (t_min + lo * step) + (h - row[lo]) / (row[lo + 1] - row[lo]) * step;
+            }
+            T[c * S + s] = t;
+        }
+    }
+    return clamped;
+}
+
 int dust_ref_get_threads(void)
 {
 #ifdef _OPENMP

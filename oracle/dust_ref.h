@@ -69,6 +69,21 @@ void dust_ref_emission(int64_t n_cells, int32_t NL, int32_t S,
                        const double* weight, const double* m_dust,
                        const double* T, double* L);
 
+/* Production variant of the temperature step (Sections 2 and 5): the table
+ * P[s*n_T + k] = grain power of grain s at T_k = t_min + k (t_max - t_min) /
+ * (n_T - 1), n_T >= 2. */
+void dust_ref_table_build(int32_t NL, int32_t S, const double* lam,
+                          const double* dlam, const double* c_abs,
+                          int32_t n_T, double t_min, double t_max, double* P);
+
+/* T[c*S + s] by linear interpolation in that table between the two points
+ * that bracket H.  H = 0 gives 0, H < 0 or non-finite NaN; H outside the
+ * table gives the end temperature (t_min or t_max).  Returns the number of
+ * pairs outside the table. */
+int64_t dust_ref_table_temperature(int64_t n_cells, int32_t S, int32_t n_T,
+                                   double t_min, double t_max, const double* P,
+                                   const double* H, double* T);
+
 /* OpenMP thread control (the oracle parallelises over cells only). */
 int dust_ref_get_threads(void);
 void dust_ref_set_threads(int n);

@@ -1,4 +1,4 @@
-// Many independent grids in one persistent launch.
+// Many independent grids in one launch.
 //
 // A batch binds (plan, buffers) per grid and a work list of (grid, cell tile)
 // items, heaviest tiles first (cost of a tile ~ NL x S of its grid).  Two

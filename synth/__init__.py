@@ -253,3 +253,28 @@ def batch_specs(n_grids: int = 64, seed: int = 3, cells_lo: float = 1e3,
         specs.append(BatchGridSpec(max(1, int(round(c * scale))), nl, ns, nz,
                                    1000 * seed + g))
     return specs
+
+
+def extra_heating(grid: Grid, n_cells: int, seed: int) -> np.ndarray:
+    """Stand-in for heating that is not absorbed radiation (e.g. collisions
+    with energetic electrons): Q[c, s] = eps_c * pi a_s^2 in the units of H
+    (W sr^-1), log10 eps_c ~ U(-8, -3), so that Q/H spans several decades
+    either side of 1 on the synthetic fields.  Float32, [C, S]."""
+    rng = np.random.default_rng(seed)
+    eps = 10.0 ** rng.uniform(-8.0, -3.0, size=n_cells)
+    area = np.pi * grid.size ** 2
+    return (eps[:, None] * area[None, :]).astype(np.float32)
+
+
+def reheat_coupling(grid: Grid, m_dust: np.ndarray, seed: int) -> np.ndarray:
+    """Coupling g[c] of the stand-in for re-propagating a cell's own emission
+    between passes of the global iteration: J_next = J0 + g[c] L[c, :].
+
+    With kappa_l = sum_s w_s C[s, l] (cross-section per unit dust mass), the
+    power one pass re-absorbs from g L is at most f_c of what the cell emitted
+    when g[c] = f_c / (m[c] max_l kappa_l); f_c ~ U(0.1, 0.5) from its own
+    seeded stream, so the iteration contracts.  Float64, [C]."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.1, 0.5, size=m_dust.shape[0])
+    kappa_max = float((grid.weight[:, None] * grid.c_abs).sum(axis=0).max())
+    return f / (np.asarray(m_dust, dtype=np.float64) * kappa_max)

@@ -304,3 +304,150 @@ def test_emission_nan_propagates():
     T = np.array([[float("nan"), 20.0]])
     L = oracle.emission(T, g.lam, g.c_abs, g.weight)
     assert np.all(np.isnan(L))
+
+
+# ----------------------------------------------------------------- extra heating (Section 2)
+
+@pytest.mark.parametrize("T", [20.0, 100.0, 1000.0])
+def test_extra_heating_alone_grey_stefan_boltzmann(T):
+    """A grey grain with no radiation field and heating Q from another source
+    balances C sigma T^4 / pi = Q (Section 2: the heating need not be
+    absorbed light)."""
+    lam, dlam = wide_grid()
+    C = 1e-14
+    grid = synth.Grid(lam, dlam, np.full((1, lam.size), C), np.ones(1), np.array([1e-7]), np.zeros(1, int))
+    Q = np.array([[C * sc.Stefan_Boltzmann * T ** 4 / math.pi]])
+    _, Tq, _ = oracle.run(grid, np.zeros((1, lam.size)), Q=Q)
+    assert abs(Tq[0, 0] / T - 1.0) < 1e-9
+
+
+@pytest.mark.parametrize("beta", [1.0, 2.0])
+@pytest.mark.parametrize("q", [0.0, 0.3, 5.0])
+def test_extra_heating_power_law_grain(beta, q):
+    """C ~ lambda^-beta: P ~ T^(4+beta), so adding Q = q H to the heating of a
+    diluted blackbody raises T by (1 + q)^(1/(4+beta))."""
+    lam, dlam = wide_grid()
+    W, Tstar = 1e-12, 8000.0
+    C = (1e-14 * (lam / 1e-6) ** -beta)[None, :]
+    grid = synth.Grid(lam, dlam, C, np.ones(1), np.array([1e-7]), np.zeros(1, int))
+    J = (W * planck_indep(lam, Tstar))[None, :]
+    H0 = oracle.heating(J, C, dlam)
+    H, T, _ = oracle.run(grid, J, Q=q * H0)
+    assert H[0, 0] == pytest.approx((1.0 + q) * H0[0, 0], rel=1e-15)
+    expect = (W * (1.0 + q)) ** (1.0 / (4.0 + beta)) * Tstar
+    assert abs(T[0, 0] / expect - 1.0) < 1e-9
+
+
+# ----------------------------------------------------------------- T table (Sections 2, 5)
+
+def test_table_nodes_are_grain_power_at_even_temperatures():
+    """The table holds Eq. 7's power at T_k = t_min + k (t_max - t_min)/(n-1);
+    checked against a test-side sum with an independent Planck function, and
+    for a grey grain against Stefan-Boltzmann."""
+    g = synth.make_grid(40, 2, [2, 1])
+    n, t0, t1 = 2000, 3.0, 1500.0
+    P = oracle.table_build(g.lam, g.dlam, g.c_abs, n, t0, t1)
+    assert P.shape == (g.c_abs.shape[0], n)
+    step = (t1 - t0) / (n - 1)
+    for s in range(P.shape[0]):
+        for k in (0, 1, 17, 999, n - 1):
+            Tk = t0 + k * step
+            ref = math.fsum(g.c_abs[s] * g.dlam * planck_indep(g.lam, Tk))
+            assert P[s, k] == pytest.approx(ref, rel=1e-13)
+    lam, dlam = wide_grid()
+    Pg = oracle.table_build(lam, dlam, np.ones((1, lam.size)), 11, 100.0, 1100.0)
+    Tk = np.linspace(100.0, 1100.0, 11)
+    np.testing.assert_allclose(Pg[0], sc.Stefan_Boltzmann * Tk ** 4 / math.pi, rtol=1e-11)
+
+
+def test_table_interpolation_is_numpy_interp():
+    """T(H) is piecewise-linear interpolation through (P_k, T_k), with the end
+    temperatures outside the table: exactly what numpy.interp computes."""
+    g = synth.make_grid(30, 2, [3, 2])
+    n, t0, t1 = 2000, 3.0, 1500.0
+    P = oracle.table_build(g.lam, g.dlam, g.c_abs, n, t0, t1)
+    S = P.shape[0]
+    rng = np.random.default_rng(7)
+    H = np.exp(rng.uniform(np.log(P[:, 0].min() / 30), np.log(P[:, -1].max() * 30), size=(500, S)))
+    H[0, :] = P[:, 5]            # exactly on a node
+    H[1, :] = P[:, -1]           # exactly the last node: in range, t_max
+    T, n_out = oracle.table_temperature(H, P, t0, t1)
+    Tk = t0 + np.arange(n) * ((t1 - t0) / (n - 1))
+    for s in range(S):
+        ref = np.interp(H[:, s], P[s], Tk)
+        np.testing.assert_allclose(T[:, s], ref, rtol=1e-13, atol=0)
+    outside = (H < P[:, 0][None, :]) | (H > P[:, -1][None, :])
+    assert n_out == int(outside.sum()) and n_out > 0
+    assert np.all(T[0] == Tk[5]) and np.all(T[1] == t1)
+
+
+def test_table_special_values_and_midpoints():
+    g = synth.make_grid(20, 1, [2])
+    n, t0, t1 = 50, 3.0, 1500.0
+    P = oracle.table_build(g.lam, g.dlam, g.c_abs, n, t0, t1)
+    step = (t1 - t0) / (n - 1)
+    k = np.arange(n - 1)
+    mid = 0.5 * (P[:, :-1] + P[:, 1:])               # [S, n-1]
+    T, n_out = oracle.table_temperature(mid.T.copy(), P, t0, t1)
+    np.testing.assert_allclose(T, (t0 + (k + 0.5) * step)[:, None].repeat(P.shape[0], 1),
+                               rtol=1e-12)
+    assert n_out == 0
+    H = np.array([[0.0, np.nan], [-1.0, np.inf]])
+    T, _ = oracle.table_temperature(H[:, :1].repeat(P.shape[0], 1), P, t0, t1)
+    assert T[0, 0] == 0.0 and np.isnan(T[1, 0])
+
+
+def test_table_underestimates_exact_root_within_one_step():
+    """P(T) is convex on the table, so its inverse is concave and the chord
+    lies below it: the table's T never exceeds the exact root and is within
+    one table step of it (equal at the nodes)."""
+    w = synth.WORKLOADS["small-1024x120x20"]
+    g = w.grid()
+    J = synth.radiation_field(w.cells().subset(np.arange(256)), g.lam).numpy().astype(np.float64)
+    H = oracle.heating(J, g.c_abs, g.dlam)
+    T_exact = oracle.temperature(H, g.lam, g.dlam, g.c_abs, g.size)
+    n, t0, t1 = 2000, 3.0, 1500.0
+    P = oracle.table_build(g.lam, g.dlam, g.c_abs, n, t0, t1)
+    T, _ = oracle.table_temperature(H, P, t0, t1)
+    inside = (T_exact > t0) & (T_exact < t1)
+    assert inside.mean() > 0.99
+    d = T_exact[inside] - T[inside]
+    assert np.all(d >= -1e-12 * T_exact[inside])
+    assert np.all(d < (t1 - t0) / (n - 1))
+    assert d.max() > 0.0
+
+
+# ----------------------------------------------------------------- re-heating loop (Section 2)
+
+def test_reheat_grey_grain_geometric_series():
+    """One grey grain: the re-absorbed power of pass n is f H_n with
+    f = g m w C, so H_n = H_0 (1 - f^(n+1)) / (1 - f) exactly."""
+    lam, dlam = wide_grid(4000)
+    Cg, w, m = 2e-14, 3.0, 0.7
+    grid = synth.Grid(lam, dlam, np.full((1, lam.size), Cg), np.array([w]), np.array([1e-7]), np.zeros(1, int))
+    J0 = np.stack([1e-10 * planck_indep(lam, 6000.0), 1e-13 * planck_indep(lam, 20000.0)])
+    f = np.array([0.4, 0.15])
+    coupling = f / (m * w * Cg)
+    passes = oracle.reheat(grid, J0, np.full(2, m), coupling, 6)
+    H0 = passes[0][0][:, 0]
+    for n, (H, T, L) in enumerate(passes):
+        expect = H0 * (1.0 - f ** (n + 1)) / (1.0 - f)
+        np.testing.assert_allclose(H[:, 0], expect, rtol=1e-12)
+
+
+def test_reheat_first_pass_and_monotone_convergence():
+    w = synth.WORKLOADS["small-1024x120x20"]
+    g = w.grid()
+    p = w.cells().subset(np.arange(64))
+    J0 = synth.radiation_field(p, g.lam).numpy().astype(np.float64)
+    coupling = synth.reheat_coupling(g, p.m_dust, 11)
+    passes = oracle.reheat(g, J0, p.m_dust, coupling, 5)
+    H, T, L = oracle.run(g, J0, p.m_dust)
+    np.testing.assert_array_equal(passes[0][1], T)
+    Ts = np.stack([t for _, t, _ in passes])
+    dT = np.diff(Ts, axis=0)
+    tiny = 1e-13 * Ts[-1]
+    assert np.all(dT[0] > 0.0) and np.all(dT >= -tiny)
+    # contraction: every later increment is smaller than the one before
+    assert np.all(dT[1:] <= dT[:-1] + tiny)
+    assert np.all(dT[-1] < 0.6 ** 3 * dT[0] + tiny)
