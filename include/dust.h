@@ -67,7 +67,17 @@ typedef enum {
        FP32 accumulation; T from an FP64 table of ln P(ln T) per grain with
        an FP64 Newton polish on its piecewise-cubic interpolant; FP32
        emission. */
-    DUST_MIXED = 1
+    DUST_MIXED = 1,
+    /* The production variant of the temperature step (Sections 2 and 5):
+       per grain, the power of Eq. 7 tabulated in FP64 at ltab_n temperatures
+       evenly spaced over [ltab_tmin, ltab_tmax] (defaults 2000, 3 K, 1500 K),
+       and T(H) by linear interpolation between the two table points that
+       bracket H.  An approximation: its error is that of the interpolation
+       (about 1e-3 relative near 20 K with the defaults, larger at lower T,
+       and T never above the exact root).  H outside the table gives the end
+       temperature and is counted in n_out_of_table.  Heating and emission
+       as in DUST_MIXED. */
+    DUST_TABLE_LINEAR = 2
 } dust_mode;
 
 /* One grid: its wavelength grid and grain set (host float64). */
@@ -87,13 +97,14 @@ typedef struct {
     int32_t mode;      /* dust_mode; default DUST_PLAIN_FP32 */
     int32_t maxit;     /* plain: Newton iteration cap, default 50 */
     double tol;        /* plain: stop when |P(T)/H - 1| <= tol, default 1e-5 */
-    int32_t ltab_n;    /* mixed: table points per grain, default 4096 (>= 16) */
+    int32_t ltab_n;    /* table points per grain: mixed default 4096 (>= 16),
+                          table-linear default 2000 (>= 16) */
     int32_t fused_kernels; /* dust_run_fused: 0 = library choice, 1 = one kernel
                               (absorb, solve and emit per cell tile), 2 = two
                               kernels (absorb + solve per tile, T written once;
                               then emit).  H never reaches device memory. */
-    double ltab_tmin;  /* mixed: lowest tabulated T (K), default 2.7 */
-    double ltab_tmax;  /* mixed: highest tabulated T (K), default 3000 */
+    double ltab_tmin;  /* lowest tabulated T (K): mixed 2.7, table-linear 3 */
+    double ltab_tmax;  /* highest tabulated T (K): mixed 3000, table-linear 1500 */
 } dust_options;
 
 /* Device-side event counters (see the conventions above). */
@@ -101,7 +112,30 @@ typedef struct {
     int64_t n_nonfinite;
     int64_t n_unconverged;
     int64_t n_out_of_table;
+    int64_t n_newton_evals;  /* DUST_PLAIN_FP32: evaluations of Eq. 7's sum
+                                (pairs x Newton iterations) */
 } dust_counters;
+
+/* Optional inputs of the temperature step (dust_solve_T_ext,
+ * dust_run_fused_ext).  A zeroed struct, or NULL, means neither.
+ *
+ *  Q           DEVICE [n_cells][ldq] float: heating from sources other than
+ *              the radiation field (Section 2 names collisions with energetic
+ *              electrons), in the units of H.  The balance of Eq. 7 is solved
+ *              for H + Q.  NULL: none.
+ *  warm_start  nonzero: on entry T holds temperatures from a previous call
+ *              (the passes of the global iteration Section 2 describes for
+ *              dust that absorbs its own emission) and DUST_PLAIN_FP32 starts
+ *              Newton there instead of at the Eq. 11 guess; entries that are
+ *              not finite and > 0 fall back to the guess.  The root is the
+ *              same; only the iteration count changes.  The table modes start
+ *              from their own O(1) lookup and ignore it. */
+typedef struct {
+    const float* Q;
+    int64_t ldq;
+    int32_t warm_start;
+    int32_t reserved;  /* must be 0 */
+} dust_solve_ext;
 
 /* Opaque, library-owned plan: the grid's derived device tables. */
 typedef struct dust_plan dust_plan;
@@ -136,6 +170,14 @@ dust_status dust_solve_T(dust_plan* plan, int64_t n_cells,
                          float* T, int64_t ldt,
                          dust_counters* counters, void* stream);
 
+/* dust_solve_T with the optional inputs of dust_solve_ext (ext may be NULL).
+ * With warm_start, T is read before it is written (in place). */
+dust_status dust_solve_T_ext(dust_plan* plan, int64_t n_cells,
+                             const float* H, int64_t ldh,
+                             const dust_solve_ext* ext,
+                             float* T, int64_t ldt,
+                             dust_counters* counters, void* stream);
+
 /* Eqs. 9-10 (Section 4.4): L[c*ldl + l] from T[c*ldt + s].  m_dust may be
  * NULL (every cell has unit dust mass). */
 dust_status dust_emit_sed(dust_plan* plan, int64_t n_cells,
@@ -148,6 +190,15 @@ dust_status dust_run_fused(dust_plan* plan, int64_t n_cells,
                            const float* J, int64_t ldj, const float* m_dust,
                            float* T, int64_t ldt, float* L, int64_t ldl,
                            dust_counters* counters, void* stream);
+
+/* dust_run_fused with the optional inputs of dust_solve_ext (ext may be
+ * NULL): Q is added to the on-chip heating; with warm_start, T is read
+ * before it is written (in place). */
+dust_status dust_run_fused_ext(dust_plan* plan, int64_t n_cells,
+                               const float* J, int64_t ldj, const float* m_dust,
+                               const dust_solve_ext* ext,
+                               float* T, int64_t ldt, float* L, int64_t ldl,
+                               dust_counters* counters, void* stream);
 
 /* Many independent grids in one launch.  A batch binds plans and
  * buffers once (host arrays of length n_grids; m_dust[g] may be NULL), builds

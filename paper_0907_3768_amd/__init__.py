@@ -22,9 +22,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdust.so")
 
 DUST_OK, DUST_EINVAL, DUST_EUNSUPPORTED, DUST_ENOMEM, DUST_EDEVICE = 0, -1, -2, -3, -4
-PLAIN, MIXED = 0, 1
+PLAIN, MIXED, TABLE_LINEAR = 0, 1, 2
 BATCH_AUTOTUNE, BATCH_REFRESH_PLANS = 1, 2
-_MODES = {"plain": PLAIN, "mixed": MIXED, PLAIN: PLAIN, MIXED: MIXED}
+_MODES = {"plain": PLAIN, "mixed": MIXED, "table": TABLE_LINEAR,
+          PLAIN: PLAIN, MIXED: MIXED, TABLE_LINEAR: TABLE_LINEAR}
+N_COUNTERS = 4  # nonfinite, unconverged, out_of_table, newton_evals
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -41,6 +43,10 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", _i32), ("maxit", _i32), ("tol", ctypes.c_double),
                 ("ltab_n", _i32), ("fused_kernels", _i32),
                 ("ltab_tmin", ctypes.c_double), ("ltab_tmax", ctypes.c_double)]
+
+
+class SolveExt(ctypes.Structure):
+    _fields_ = [("Q", _vp), ("ldq", _i64), ("warm_start", _i32), ("reserved", _i32)]
 
 
 class DustError(RuntimeError):
@@ -76,8 +82,11 @@ def lib():
         "dust_plan_info": [_vp, _vp, _vp, _vp],
         "dust_absorb": [_vp, _i64, _vp, _i64, _vp, _i64, _vp],
         "dust_solve_T": [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp],
+        "dust_solve_T_ext": [_vp, _i64, _vp, _i64, ctypes.POINTER(SolveExt), _vp, _i64, _vp, _vp],
         "dust_emit_sed": [_vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp],
         "dust_run_fused": [_vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp],
+        "dust_run_fused_ext": [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(SolveExt), _vp, _i64,
+                               _vp, _i64, _vp, _vp],
         "dust_batch_create": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
                               ctypes.POINTER(_vp)],
         "dust_batch_launch": [_vp, _vp],
@@ -125,9 +134,20 @@ def _rows(t, width, name):
 
 
 def new_counters(device="cuda"):
-    """A zeroed device dust_counters (int64 x 3: nonfinite, unconverged, out_of_table)."""
+    """A zeroed device dust_counters (int64 x 4: nonfinite, unconverged,
+    out_of_table, newton_evals)."""
     import torch
-    return torch.zeros(3, dtype=torch.int64, device=device)
+    return torch.zeros(N_COUNTERS, dtype=torch.int64, device=device)
+
+
+def _ext(Q, warm_start, width):
+    """A dust_solve_ext for (Q, warm_start), or None when neither is given."""
+    if Q is None and not warm_start:
+        return None
+    if Q is None:
+        return SolveExt(None, 0, 1, 0)
+    pq, ldq = _rows(Q, width, "Q")
+    return SolveExt(pq, ldq, 1 if warm_start else 0, 0)
 
 
 class Plan:
@@ -179,12 +199,22 @@ class Plan:
         _check(lib().dust_absorb(self._h, n, pj, ldj, ph, ldh, _stream(stream)))
         return H
 
-    def solve(self, H, T=None, counters=None, stream=None):
+    def solve(self, H, T=None, counters=None, stream=None, Q=None, warm_start=False):
+        """Eq. 7 for every pair.  Q: extra heating added to H; warm_start: T
+        already holds a previous solution, where the plain Newton starts."""
         n = H.shape[0]
+        if warm_start and T is None:
+            raise ValueError("warm_start needs T holding the previous temperatures")
         T = self._alloc(n, self.n_grains, H) if T is None else T
         ph, ldh = _rows(H, self.n_grains, "H")
         pt, ldt = _rows(T, self.n_grains, "T")
-        _check(lib().dust_solve_T(self._h, n, ph, ldh, pt, ldt, _ptr(counters), _stream(stream)))
+        x = _ext(Q, warm_start, self.n_grains)
+        if x is None:
+            _check(lib().dust_solve_T(self._h, n, ph, ldh, pt, ldt, _ptr(counters),
+                                      _stream(stream)))
+        else:
+            _check(lib().dust_solve_T_ext(self._h, n, ph, ldh, ctypes.byref(x), pt, ldt,
+                                          _ptr(counters), _stream(stream)))
         return T
 
     def emit(self, T, m_dust=None, L=None, stream=None):
@@ -195,27 +225,38 @@ class Plan:
         _check(lib().dust_emit_sed(self._h, n, pt, ldt, _ptr(m_dust), pl, ldl, _stream(stream)))
         return L
 
-    def fused(self, J, m_dust=None, T=None, L=None, counters=None, stream=None):
+    def fused(self, J, m_dust=None, T=None, L=None, counters=None, stream=None, Q=None,
+              warm_start=False):
+        """absorb -> solve -> emit in one launch per tile; Q and warm_start as
+        in ``solve``."""
         n = J.shape[0]
+        if warm_start and T is None:
+            raise ValueError("warm_start needs T holding the previous temperatures")
         T = self._alloc(n, self.n_grains, J) if T is None else T
         L = self._alloc(n, self.n_lambda, J) if L is None else L
         pj, ldj = _rows(J, self.n_lambda, "J")
         pt, ldt = _rows(T, self.n_grains, "T")
         pl, ldl = _rows(L, self.n_lambda, "L")
-        _check(lib().dust_run_fused(self._h, n, pj, ldj, _ptr(m_dust), pt, ldt, pl, ldl,
-                                    _ptr(counters), _stream(stream)))
+        x = _ext(Q, warm_start, self.n_grains)
+        if x is None:
+            _check(lib().dust_run_fused(self._h, n, pj, ldj, _ptr(m_dust), pt, ldt, pl, ldl,
+                                        _ptr(counters), _stream(stream)))
+        else:
+            _check(lib().dust_run_fused_ext(self._h, n, pj, ldj, _ptr(m_dust), ctypes.byref(x),
+                                            pt, ldt, pl, ldl, _ptr(counters), _stream(stream)))
         return T, L
 
-    def run(self, J, m_dust=None, counters=None, stream=None):
+    def run(self, J, m_dust=None, counters=None, stream=None, Q=None, T=None,
+            warm_start=False):
         """absorb -> solve -> emit as three launches; returns (H, T, L)."""
         H = self.absorb(J, stream=stream)
-        T = self.solve(H, counters=counters, stream=stream)
+        T = self.solve(H, T=T, counters=counters, stream=stream, Q=Q, warm_start=warm_start)
         L = self.emit(T, m_dust, stream=stream)
         return H, T, L
 
 
 class Batch:
-    """Many grids in one persistent launch recorded in a HIP graph (dust_batch)."""
+    """Many grids in one launch recorded in a HIP graph (dust_batch)."""
 
     def __init__(self, plans: Sequence[Plan], J, m_dust, T, L, counters=None, autotune=True,
                  refresh_plans=False):

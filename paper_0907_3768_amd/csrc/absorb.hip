@@ -6,7 +6,8 @@
 // the 16 x S block of H with coalesced stores, undoing the per-grain power
 // of two.
 //   DUST_PLAIN_FP32: v_mfma_f32_16x16x4_f32 (exact FP32 products).
-//   DUST_MIXED:      v_mfma_f32_16x16x32_bf16 on hi+lo splits,
+//   DUST_MIXED, DUST_TABLE_LINEAR:
+//                    v_mfma_f32_16x16x32_bf16 on hi+lo splits,
 //                    J_hi K_hi + J_hi K_lo + J_lo K_hi, FP32 accumulation.
 #include "fused_body.h"
 
@@ -34,7 +35,7 @@ hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj,
                       int64_t ldh, hipStream_t st) {
     const dim3 grid((unsigned)((C + 15) / 16));
     const size_t lds = sizeof(float) * 16 * v.Sp + STAGE_BYTES;
-    if (v.mode == DUST_MIXED)
+    if (table_mode(v.mode))  // bf16 hi+lo heating
         hipLaunchKernelGGL((absorb_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v, C, J,
                            ldj, H, ldh);
     else

@@ -66,19 +66,20 @@ dust_status resolve_options(const dust_options* in, dust_options* o) {
     dust_options d;
     memset(&d, 0, sizeof d);
     if (in) d = *in;
-    if (d.mode != DUST_PLAIN_FP32 && d.mode != DUST_MIXED)
-        return set_error(DUST_EINVAL, "mode must be DUST_PLAIN_FP32 or DUST_MIXED");
+    if (d.mode != DUST_PLAIN_FP32 && d.mode != DUST_MIXED && d.mode != DUST_TABLE_LINEAR)
+        return set_error(DUST_EINVAL, "mode must be DUST_PLAIN_FP32, DUST_MIXED or DUST_TABLE_LINEAR");
+    const bool lin = d.mode == DUST_TABLE_LINEAR;
     if (d.maxit < 0) return set_error(DUST_EINVAL, "maxit must be >= 0");
     if (d.maxit == 0) d.maxit = 50;
     if (!(d.tol >= 0.0) || !isfinite(d.tol)) return set_error(DUST_EINVAL, "tol must be finite and >= 0");
     if (d.tol == 0.0) d.tol = 1e-5;
     if (d.ltab_n < 0 || (d.ltab_n > 0 && d.ltab_n < 16) || d.ltab_n > MAX_TABLE / 4)
         return set_error(DUST_EINVAL, "ltab_n must be 0 (default) or in [16, 16383]");
-    if (d.ltab_n == 0) d.ltab_n = 4096;
+    if (d.ltab_n == 0) d.ltab_n = lin ? 2000 : 4096;
     if (d.fused_kernels < 0 || d.fused_kernels > 2)
         return set_error(DUST_EINVAL, "fused_kernels must be 0, 1 or 2");
-    if (d.ltab_tmin == 0.0) d.ltab_tmin = 2.7;
-    if (d.ltab_tmax == 0.0) d.ltab_tmax = 3000.0;
+    if (d.ltab_tmin == 0.0) d.ltab_tmin = lin ? 3.0 : 2.7;
+    if (d.ltab_tmax == 0.0) d.ltab_tmax = lin ? 1500.0 : 3000.0;
     if (!(d.ltab_tmin > 0.0) || !(d.ltab_tmax > d.ltab_tmin) || !isfinite(d.ltab_tmax) ||
         d.ltab_tmin < 1e-2 || d.ltab_tmax > 1e6)
         return set_error(DUST_EINVAL, "need 0.01 <= ltab_tmin < ltab_tmax <= 1e6");
@@ -97,7 +98,7 @@ void free_plan(dust_plan* p) {
     void* ptrs[] = {p->d_lam, p->d_dlam, p->d_cabs, p->d_w,   p->d_size, p->d_es,   p->d_nu,
                     p->d_hscale, p->d_hinv, p->d_gs, p->d_kf,  p->d_kb,   p->d_em,   p->d_khi,
                     p->d_klo, p->d_kdb,  p->d_c2l,  p->d_fwd, p->d_inv, p->d_ylo,  p->d_yhi,
-                    p->d_dyinv, p->d_texp, p->d_lntab, p->d_F};
+                    p->d_dyinv, p->d_texp, p->d_lntab, p->d_F, p->d_kidx};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -180,10 +181,14 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     p->NL = NL; p->S = S; p->NLp = NLp; p->Sp = Sp;
     p->ge = ge;
     p->N = o.ltab_n;
-    p->M = o.ltab_n < 256 ? o.ltab_n : 256;  // inverse-table nodes (a start for Newton only)
+    const bool lin = o.mode == DUST_TABLE_LINEAR;
+    // nodes of the inverse table (mixed: a start for Newton only) or of the
+    // search brackets (table-linear)
+    p->M = lin ? 2048 : (o.ltab_n < 256 ? o.ltab_n : 256);
     p->lnTmin = log(o.ltab_tmin);
     p->hstep = (log(o.ltab_tmax) - log(o.ltab_tmin)) / (p->N - 1);
-    const bool mixed = o.mode == DUST_MIXED;
+    const double tstep = (o.ltab_tmax - o.ltab_tmin) / (p->N - 1);
+    const bool mixed = table_mode(o.mode);
 
 #define ALLOC(ptr, n)                                              \
     if ((e = dev_alloc(&(ptr), (n))) != hipSuccess) {               \
@@ -209,7 +214,11 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     ALLOC(p->d_c2l, NL);
     if (mixed) {
         ALLOC(p->d_fwd, (size_t)S * p->N);
-        ALLOC(p->d_inv, (size_t)S * p->M);
+        if (lin) {
+            ALLOC(p->d_kidx, (size_t)S * p->M);
+        } else {
+            ALLOC(p->d_inv, (size_t)S * p->M);
+        }
         ALLOC(p->d_ylo, S);
         ALLOC(p->d_yhi, S);
         ALLOC(p->d_dyinv, S);
@@ -236,7 +245,8 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     std::vector<double2> lntab;
     if (mixed) {
         texp.resize(p->N);
-        for (int k = 0; k < p->N; ++k) texp[k] = exp(p->lnTmin + k * p->hstep);
+        for (int k = 0; k < p->N; ++k)
+            texp[k] = lin ? o.ltab_tmin + k * tstep : exp(p->lnTmin + k * p->hstep);
         lntab.resize(256);
         for (int i = 0; i < 256; ++i) {
             const double c = 1.0 + i / 256.0;
@@ -284,6 +294,11 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     v.inv_hstep = 1.0 / p->hstep;
     v.texp = p->d_texp;
     v.lntab = p->d_lntab;
+    v.kidx = p->d_kidx;
+    v.tstep = tstep;
+    v.q = nullptr;
+    v.ldq = 0;
+    v.warm = 0;
 
     if ((e = launch_prepare(p, nullptr)) != hipSuccess) {
         free_plan(p);
@@ -348,16 +363,40 @@ dust_status dust_absorb(dust_plan* p, int64_t C, const float* J, int64_t ldj, fl
     return e == hipSuccess ? DUST_OK : hip_error(e, "absorb launch");
 }
 
-dust_status dust_solve_T(dust_plan* p, int64_t C, const float* H, int64_t ldh, float* T,
-                         int64_t ldt, dust_counters* cnt, void* stream) {
+// The per-call view: the plan's tables plus the optional solve inputs.
+static dust_status apply_ext(const dust_plan* p, const dust_solve_ext* x, int64_t C,
+                             PlanView* v) {
+    *v = p->view;
+    if (!x) return DUST_OK;
+    if (x->reserved != 0) return set_error(DUST_EINVAL, "dust_solve_ext.reserved must be 0");
+    if (x->Q) {
+        dust_status st = check_buf(x->Q, x->ldq, p->S, C, "Q");
+        if (st != DUST_OK) return st;
+        v->q = x->Q;
+        v->ldq = x->ldq;
+    }
+    v->warm = x->warm_start != 0;
+    return DUST_OK;
+}
+
+dust_status dust_solve_T_ext(dust_plan* p, int64_t C, const float* H, int64_t ldh,
+                             const dust_solve_ext* ext, float* T, int64_t ldt,
+                             dust_counters* cnt, void* stream) {
     g_last_error.clear();
     dust_status st;
     if ((st = check_common(p, C)) != DUST_OK) return st;
     if ((st = check_buf(H, ldh, p->S, C, "H")) != DUST_OK) return st;
     if ((st = check_buf(T, ldt, p->S, C, "T")) != DUST_OK) return st;
     if (cnt && ((uintptr_t)cnt & 7u)) return set_error(DUST_EINVAL, "counters must be 8-byte aligned");
-    hipError_t e = launch_solve(p->view, C, H, ldh, T, ldt, cnt, (hipStream_t)stream);
+    PlanView v;
+    if ((st = apply_ext(p, ext, C, &v)) != DUST_OK) return st;
+    hipError_t e = launch_solve(v, C, H, ldh, T, ldt, cnt, (hipStream_t)stream);
     return e == hipSuccess ? DUST_OK : hip_error(e, "solve launch");
+}
+
+dust_status dust_solve_T(dust_plan* p, int64_t C, const float* H, int64_t ldh, float* T,
+                         int64_t ldt, dust_counters* cnt, void* stream) {
+    return dust_solve_T_ext(p, C, H, ldh, nullptr, T, ldt, cnt, stream);
 }
 
 dust_status dust_emit_sed(dust_plan* p, int64_t C, const float* T, int64_t ldt, const float* m,
@@ -372,9 +411,9 @@ dust_status dust_emit_sed(dust_plan* p, int64_t C, const float* T, int64_t ldt, 
     return e == hipSuccess ? DUST_OK : hip_error(e, "emit launch");
 }
 
-dust_status dust_run_fused(dust_plan* p, int64_t C, const float* J, int64_t ldj, const float* m,
-                           float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
-                           void* stream) {
+dust_status dust_run_fused_ext(dust_plan* p, int64_t C, const float* J, int64_t ldj,
+                               const float* m, const dust_solve_ext* ext, float* T, int64_t ldt,
+                               float* L, int64_t ldl, dust_counters* cnt, void* stream) {
     g_last_error.clear();
     dust_status st;
     if ((st = check_common(p, C)) != DUST_OK) return st;
@@ -383,12 +422,21 @@ dust_status dust_run_fused(dust_plan* p, int64_t C, const float* J, int64_t ldj,
     if ((st = check_buf(L, ldl, p->NL, C, "L")) != DUST_OK) return st;
     if (m && ((uintptr_t)m & 3u)) return set_error(DUST_EINVAL, "m_dust is not 4-byte aligned");
     if (cnt && ((uintptr_t)cnt & 7u)) return set_error(DUST_EINVAL, "counters must be 8-byte aligned");
+    PlanView v;
+    if ((st = apply_ext(p, ext, C, &v)) != DUST_OK) return st;
+    const hipStream_t sm = (hipStream_t)stream;
     hipError_t e = (p->opt.fused_kernels == 2)
-                       ? launch_absorb_solve(p->view, C, J, ldj, T, ldt, cnt, (hipStream_t)stream)
-                       : launch_fused(p->view, C, J, ldj, m, T, ldt, L, ldl, cnt, (hipStream_t)stream);
+                       ? launch_absorb_solve(v, C, J, ldj, T, ldt, cnt, sm)
+                       : launch_fused(v, C, J, ldj, m, T, ldt, L, ldl, cnt, sm);
     if (e == hipSuccess && p->opt.fused_kernels == 2)
-        e = launch_emit(p->view, C, T, ldt, m, L, ldl, (hipStream_t)stream);
+        e = launch_emit(v, C, T, ldt, m, L, ldl, sm);
     return e == hipSuccess ? DUST_OK : hip_error(e, "fused launch");
+}
+
+dust_status dust_run_fused(dust_plan* p, int64_t C, const float* J, int64_t ldj, const float* m,
+                           float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
+                           void* stream) {
+    return dust_run_fused_ext(p, C, J, ldj, m, nullptr, T, ldt, L, ldl, cnt, stream);
 }
 
 }  // extern "C"

@@ -21,18 +21,30 @@ __device__ __forceinline__ void count(int64_t* field) {
     atomicAdd(reinterpret_cast<unsigned long long*>(field), 1ull);
 }
 
+// Adds the sum of `n` over the wave to a counter with one atomic.  Every lane
+// of the wave must call it.
+__device__ __forceinline__ void wave_count_add(int64_t* field, int n) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) n += __shfl_xor(n, off, 64);
+    if ((threadIdx.x & 63) == 0 && n != 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(field), (unsigned long long)n);
+}
+
 // ---------------------------------------------------------------------------
 // Plain FP32 solve of Eq. 7 for one pair (Section 4.3): Newton's method on
 // ln P(T) = ln H in the variable ln T from the Eq. 11 guess, with a bracket
 // safeguard.  Stops when |ln(P/H)| <= tol and then applies the Newton step
 // already computed.  `kb` is the grain's row of K' c1 lam^-5 (stride 1);
-// `nu` the wavelength table.  Returns T.
+// `nu` the wavelength table.  A finite tstart > 0 (a previous solution)
+// replaces the guess as the starting point.  Returns T; *evals receives the
+// number of evaluations of the sum.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float solve_newton_f32(const float* __restrict__ kb,
                                                   const float* __restrict__ nu,
                                                   int NL, float hs, float gs,
-                                                  float tol, int maxit,
-                                                  dust_counters* cnt) {
+                                                  float tol, int maxit, float tstart,
+                                                  int* evals, dust_counters* cnt) {
+    *evals = 0;
     if (!(hs >= 0.0f) || __builtin_isinf(hs)) {
         if (cnt) count(&cnt->n_nonfinite);
         return __builtin_nanf("");
@@ -40,10 +52,11 @@ __device__ __forceinline__ float solve_newton_f32(const float* __restrict__ kb,
     if (hs == 0.0f) return 0.0f;
 
     const float lnH = logf(hs);
-    float lnT = guess_lnT(hs, gs);
+    float lnT = (tstart > 0.0f && tstart < INFINITY) ? logf(tstart) : guess_lnT(hs, gs);
     float lo = -INFINITY, hi = INFINITY;
     bool done = false;
-    for (int it = 0; it < maxit; ++it) {
+    int it = 0;
+    for (; it < maxit; ++it) {
         const float invT = expf(-lnT);
         float p0 = 0.f, p1 = 0.f, d0 = 0.f, d1 = 0.f;
         int l = 0;
@@ -75,9 +88,17 @@ __device__ __forceinline__ float solve_newton_f32(const float* __restrict__ kb,
         }
         const float P = p0 + p1;
         const float D = d0 + d1;  // = -sum K' B x / (ln 2 (1 - e^-x))
-        if (!(P > 0.0f)) {        // every term underflowed: T is far too low
+        // A start far from the root (a warm start can be anywhere) may leave
+        // the sum unusable; step towards the Eq. 11 guess, or bisect once
+        // the other end of the bracket is known.
+        if (!(P < INFINITY)) {    // inf or NaN (1 - 2^-t rounded to 0): T far too high
+            hi = lnT;
+            lnT = (lo > -INFINITY) ? 0.5f * (lo + hi) : fminf(lnT - 1.0f, guess_lnT(hs, gs));
+            continue;
+        }
+        if (!(P > 0.0f)) {        // every term underflowed: T far too low
             lo = lnT;
-            lnT = (hi < INFINITY) ? 0.5f * (lo + hi) : lnT + 1.0f;
+            lnT = (hi < INFINITY) ? 0.5f * (lo + hi) : fmaxf(lnT + 1.0f, guess_lnT(hs, gs));
             continue;
         }
         const float r = logf(P) - lnH;           // ln(P / H)
@@ -94,6 +115,7 @@ __device__ __forceinline__ float solve_newton_f32(const float* __restrict__ kb,
                                                      : lnT - copysignf(1.0f, r);
         lnT = next;
     }
+    *evals = done ? it + 1 : it;
     if (!done && cnt) count(&cnt->n_unconverged);
     return expf(lnT);
 }
@@ -295,6 +317,48 @@ __device__ inline float wave_solve_pending(const PlanView& v, int s, double hs,
         if (!ok) count(&cnt->n_unconverged);
     }
     return (float)exp(lnT);
+}
+
+// ---------------------------------------------------------------------------
+// Table-linear solve for one pair (the production variant of Sections 2 and
+// 5): with P'_k the grain's FP64 table at T_k = tmin + k tstep, find k with
+// P'_k <= H' < P'_{k+1} and interpolate T linearly between T_k and T_{k+1}.
+// The search starts from the bracket [kidx[j], kidx[j+1] + 1] of the ln P'
+// node j below ln H' (a few table points wide) and falls back to the whole
+// table if rounding put H' outside it.  H' outside the table gives the end
+// temperature (counted).  hs is an FP32 value in the plan's scaled units.
+// ---------------------------------------------------------------------------
+__device__ inline float table_linear_T(const PlanView& v, int s, float hs, dust_counters* cnt) {
+    if (!(hs >= 0.0f) || __builtin_isinf(hs)) {
+        if (cnt) count(&cnt->n_nonfinite);
+        return __builtin_nanf("");
+    }
+    if (hs == 0.0f) return 0.0f;
+    const int N = v.N;
+    const double* P = v.fwd + (int64_t)s * N;
+    const double h = (double)hs;
+    const double p0 = P[0], pn = P[N - 1];
+    if (!(h >= p0 && h < pn)) {
+        if (cnt && h != pn) count(&cnt->n_out_of_table);
+        return (float)(h < p0 ? v.texp[0] : v.texp[N - 1]);
+    }
+    const double u = (ln_f32_value(h, v.lntab) - v.ylo[s]) * v.dyinv[s];
+    const int j = (u > 0.0) ? (u < (double)(v.M - 2) ? (int)u : v.M - 2) : 0;
+    const int* kx = v.kidx + (int64_t)s * v.M;
+    int a = kx[j], b = kx[j + 1] + 1;  // kidx <= N - 2, so b <= N - 1
+    double pa = P[a], pb = P[b];
+    if (!(pa <= h && h < pb)) {
+        a = 0;
+        b = N - 1;
+        pa = p0;
+        pb = pn;
+    }
+    while (b - a > 1) {  // invariant: P'_a <= h < P'_b
+        const int mid = (a + b) >> 1;
+        const double pm = P[mid];
+        if (pm <= h) { a = mid; pa = pm; } else { b = mid; pb = pm; }
+    }
+    return (float)(v.texp[a] + (h - pa) / (pb - pa) * v.tstep);
 }
 
 // Capacity of a block's LDS list of pending pairs.

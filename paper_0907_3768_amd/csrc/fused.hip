@@ -43,6 +43,9 @@ hipError_t launch_as_ntw(const PlanView& v, int64_t C, const float* J, int64_t l
     if (v.mode == DUST_MIXED)
         hipLaunchKernelGGL((absorb_solve_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v,
                            C, J, ldj, T, ldt, cnt);
+    else if (v.mode == DUST_TABLE_LINEAR)
+        hipLaunchKernelGGL((absorb_solve_kernel<DUST_TABLE_LINEAR, NTW>), grid, dim3(256), lds,
+                           st, v, C, J, ldj, T, ldt, cnt);
     else
         hipLaunchKernelGGL((absorb_solve_kernel<DUST_PLAIN_FP32, NTW>), grid, dim3(256), lds, st,
                            v, C, J, ldj, T, ldt, cnt);
@@ -58,6 +61,9 @@ hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj,
     if (v.mode == DUST_MIXED)
         hipLaunchKernelGGL((fused_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v, C, J, ldj,
                            m, T, ldt, L, ldl, cnt);
+    else if (v.mode == DUST_TABLE_LINEAR)
+        hipLaunchKernelGGL((fused_kernel<DUST_TABLE_LINEAR, NTW>), grid, dim3(256), lds, st, v, C,
+                           J, ldj, m, T, ldt, L, ldl, cnt);
     else
         hipLaunchKernelGGL((fused_kernel<DUST_PLAIN_FP32, NTW>), grid, dim3(256), lds, st, v, C, J,
                            ldj, m, T, ldt, L, ldl, cnt);

@@ -53,7 +53,7 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
     };
     auto store_j = [&](int buf, float x0, float x1) {
         char* base = sStage + buf * STAGE_BUF_BYTES;
-        if constexpr (MODE == DUST_MIXED) {
+        if constexpr (table_mode(MODE)) {
             // [hi|lo][16 rows][STAGE_ROW_BF16] bf16; a pair of columns per 32-bit store
             typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
             const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
         const int k0 = step * 32;
         const int buf = step & 1;
         if (step + 1 < nsteps) load_j(k0 + 32, x0, x1);  // prefetch the next chunk
-        if constexpr (MODE == DUST_MIXED) {
+        if constexpr (table_mode(MODE)) {
             const __bf16* b = reinterpret_cast<const __bf16*>(sStage + buf * STAGE_BUF_BYTES);
             const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(b + row * STAGE_ROW_BF16 + kq * 8);
             const bf16x8 alo = *reinterpret_cast<const bf16x8*>(
@@ -139,10 +139,13 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
 // LDS used by the solve phase for its list of pending pairs.
 constexpr int SOLVE_LDS_BYTES = (PENDING_CAP + 4) * (int)sizeof(int);
 
-// Phase 2: solve every pair of the tile from sH (scaled heating), write T and
-// leave 1/T in sH.  Pairs outside the mixed table are marked by a negative
-// sH (-H'), listed in LDS and solved exactly by the block's waves in turn;
-// the list is rebuilt until no mark is left.
+// Phase 2: solve every pair of the tile from sH (scaled heating, to which
+// the optional extra heating Q is added), write T and leave 1/T in sH.
+// Mixed: pairs outside the table are marked by a negative sH (-H'), listed
+// in LDS and solved exactly by the block's waves in turn; the list is
+// rebuilt until no mark is left.  Plain: Newton from the Eq. 11 guess or,
+// with a warm start, from the T already in the output.  Table-linear:
+// interpolation in the grain's table.
 template <int MODE, int TC>
 __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64_t C,
                                             float* __restrict__ T, int64_t ldt,
@@ -154,15 +157,17 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
         if (threadIdx.x == 0) *sCount = 0;
         __syncthreads();
     }
+    int evals = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int cc = i / v.Sp, s = i - cc * v.Sp;
         const int64_t c = c0 + cc;
         const bool pair = s < v.S && c < C;
         float inv = __builtin_inff();
         if (pair) {
+            float h = sH[i];
+            if (v.q) h += v.q[c * v.ldq + s] * v.hscale[s];
             float t;
             if constexpr (MODE == DUST_MIXED) {
-                const float h = sH[i];
                 double lnT0;
                 if (table_lookup_f64(v, s, (double)h, &t, &lnT0, cnt) != 0) {
                     const int k = atomicAdd(sCount, 1);
@@ -170,14 +175,22 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
                     sH[i] = -h;  // pending: solved below
                     continue;
                 }
+            } else if constexpr (MODE == DUST_TABLE_LINEAR) {
+                t = table_linear_T(v, s, h, cnt);
             } else {
-                t = solve_newton_f32(v.kb + (int64_t)s * v.NLp, v.nu, v.NL, sH[i], v.gs[s],
-                                     v.tol, v.maxit, cnt);
+                const float t0 = v.warm ? T[c * ldt + s] : 0.0f;
+                int ev;
+                t = solve_newton_f32(v.kb + (int64_t)s * v.NLp, v.nu, v.NL, h, v.gs[s], v.tol,
+                                     v.maxit, t0, &ev, cnt);
+                evals += ev;
             }
             T[c * ldt + s] = t;
             inv = inv_temperature(t);
         }
         sH[i] = inv;
+    }
+    if constexpr (MODE == DUST_PLAIN_FP32) {
+        if (cnt) wave_count_add(&cnt->n_newton_evals, evals);
     }
     if constexpr (MODE == DUST_MIXED) {
         __syncthreads();

@@ -57,8 +57,19 @@ struct PlanView {
     int N, M;
     double lnTmin, hstep;  // ln T_k = lnTmin + k hstep
     double inv_hstep;
-    const double* texp;    // [N] T_k = exp(lnTmin + k hstep)
+    const double* texp;    // [N] T_k: exp(lnTmin + k hstep) (mixed),
+                           //      tmin + k tstep (table-linear)
     const double2* lntab;  // [256] (ln c_i, 1 / c_i), c_i = 1 + i / 256
+    // table-linear: fwd holds P'_s(T_k) itself; ylo/yhi/dyinv describe
+    // M uniform nodes in ln P' and kidx[s][j] the last table point whose
+    // ln P' is <= node j (a bracket for the search)
+    const int* kidx;       // [S][M]
+    double tstep;          // T_{k+1} - T_k
+    // Per-call inputs of the temperature step (dust_solve_ext); zero in the
+    // plan's own copy.
+    const float* q;        // [C][ldq] extra heating (unscaled units of H), or null
+    int64_t ldq;
+    int warm;              // plain: start Newton from the T already in the output
 };
 
 }  // namespace dust
@@ -77,8 +88,9 @@ struct dust_plan {
     float *d_nu, *d_hscale, *d_hinv, *d_gs, *d_kf, *d_kb, *d_em;
     __bf16 *d_khi, *d_klo;
     double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv, *d_fwd, *d_texp;
-    double* d_F;  // [N][NL] Planck factors of the table temperatures (mixed)
+    double* d_F;  // [N][NL] Planck factors of the table temperatures
     double2 *d_inv, *d_lntab;
+    int* d_kidx;  // table-linear search brackets [S][M]
     dust::PlanView view;
 };
 
@@ -94,6 +106,8 @@ hipError_t launch_absorb(const PlanView& v, int64_t C, const float* J, int64_t l
                          float* H, int64_t ldh, hipStream_t st);
 hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ldh,
                         float* T, int64_t ldt, dust_counters* cnt, hipStream_t st);
+// Modes whose heating runs on bf16 hi+lo MFMA and whose T comes from a table.
+__host__ __device__ constexpr bool table_mode(int mode) { return mode != DUST_PLAIN_FP32; }
 hipError_t launch_emit(const PlanView& v, int64_t C, const float* T, int64_t ldt,
                        const float* m, float* L, int64_t ldl, hipStream_t st);
 hipError_t launch_absorb_solve(const PlanView& v, int64_t C, const float* J, int64_t ldj,

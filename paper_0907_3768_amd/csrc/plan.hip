@@ -12,6 +12,10 @@
 //  inv   (mixed mode): the inverse function ln T(y) and its derivative at
 //        uniform steps of y, from Newton on the forward table's piecewise
 //        cubic, so that a lookup starts next to its root.
+//  table-linear mode: the same matrix product gives P'(T_k) itself at evenly
+//        spaced T_k (the production table of Sections 2 and 5); kidx gives,
+//        at uniform steps of ln P', the last table point below, so that a
+//        lookup searches only a few points.
 #include "device_common.h"
 
 namespace dust {
@@ -66,12 +70,14 @@ __global__ __launch_bounds__(256) void planck_factor_kernel(PlanView v, double* 
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
     if (l >= v.NL) return;
-    const double invT = exp(-(v.lnTmin + k * v.hstep));
+    const double invT = (v.mode == DUST_TABLE_LINEAR) ? 1.0 / v.texp[k]
+                                                      : exp(-(v.lnTmin + k * v.hstep));
     F[(int64_t)k * v.NL + l] = 1.0 / expm1_pos(v.c2l[l] * invT);  // 0 once e^x overflows
 }
 
-// y[s][k] = ln sum_l W[s][l] F[k][l]: FP64 GEMM, 16 x 16 output tile per
-// 256-thread block, 16-wide chunks of l staged in LDS.
+// y[s][k] = ln sum_l W[s][l] F[k][l] (table-linear: the sum itself): FP64
+// GEMM, 16 x 16 output tile per 256-thread block, 16-wide chunks of l staged
+// in LDS.
 __global__ __launch_bounds__(256) void ltab_gemm_kernel(PlanView v, const double* __restrict__ F,
                                                         double* fwd) {
     __shared__ double sW[16][17];
@@ -89,7 +95,35 @@ __global__ __launch_bounds__(256) void ltab_gemm_kernel(PlanView v, const double
         for (int i = 0; i < 16; ++i) acc = fma(sW[ty][i], sF[tx][i], acc);
         __syncthreads();
     }
-    if (s < v.S && k < v.N) fwd[(int64_t)s * v.N + k] = log(acc);
+    if (s < v.S && k < v.N)
+        fwd[(int64_t)s * v.N + k] = (v.mode == DUST_TABLE_LINEAR) ? acc : log(acc);
+}
+
+// Table-linear: one thread per (grain, node); node j sits at
+// ln P' = ylo + j (yhi - ylo) / (M - 1) and kidx[s][j] is the largest k in
+// [0, N-2] with ln P'_k <= that value (0 if none).
+__global__ __launch_bounds__(256) void kidx_kernel(PlanView v, const double* __restrict__ fwd,
+                                                   int* kidx, double* ylo, double* yhi,
+                                                   double* dyinv) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (j >= v.M) return;
+    const int N = v.N;
+    const double* P = fwd + (int64_t)s * N;
+    const double y0 = log(P[0]), y1 = log(P[N - 1]);
+    const double dinv = (v.M - 1) / (y1 - y0);
+    if (j == 0) {
+        ylo[s] = y0;
+        yhi[s] = y1;
+        dyinv[s] = dinv;
+    }
+    const double yj = (j == v.M - 1) ? y1 : y0 + j / dinv;
+    int lo = 0, hi = N - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (log(P[mid]) <= yj) lo = mid; else hi = mid - 1;
+    }
+    kidx[(int64_t)s * v.M + j] = lo;
 }
 
 // One thread per (grain, inverse node): ln T at y_j = ylo + j dy, by Newton
@@ -139,7 +173,7 @@ hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
                        p->d_w, p->d_es, p->ge, p->d_nu, p->d_kf, p->d_khi, p->d_klo, p->d_kb,
                        p->d_em, p->d_kdb, p->d_c2l);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || v.mode != DUST_MIXED) return e;
+    if (e != hipSuccess || !table_mode(v.mode)) return e;
     dim3 gf((v.NL + 255) / 256, v.N);
     hipLaunchKernelGGL(planck_factor_kernel, gf, dim3(256), 0, st, v, p->d_F);
     e = hipGetLastError();
@@ -149,6 +183,11 @@ hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g3((v.M + 255) / 256, v.S);
+    if (v.mode == DUST_TABLE_LINEAR) {
+        hipLaunchKernelGGL(kidx_kernel, g3, dim3(256), 0, st, v, (const double*)p->d_fwd,
+                           p->d_kidx, p->d_ylo, p->d_yhi, p->d_dyinv);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(inv_kernel, g3, dim3(256), 0, st, v, (const double*)p->d_fwd, p->d_inv,
                        p->d_ylo, p->d_yhi, p->d_dyinv);
     return hipGetLastError();

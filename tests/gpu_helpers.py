@@ -23,18 +23,27 @@ def strided_rows(n_cells, n_sample):
     return np.arange(n_sample) * step
 
 
-def oracle_on_rows(grid, J_rows, m_rows):
-    """FP64 oracle on the exact FP32 J rows the GPU consumed (upcast)."""
-    return oracle.run(grid, np.asarray(J_rows, dtype=np.float64), m_rows)
+# The production T-table of Sections 2 and 5: 2000 points, 3 K to 1500 K.
+TABLE = (2000, 3.0, 1500.0)
+
+
+def oracle_on_rows(grid, J_rows, m_rows, Q=None, table=None):
+    """FP64 oracle on the exact FP32 J (and Q) rows the GPU consumed (upcast)."""
+    Q = None if Q is None else np.asarray(Q, dtype=np.float64)
+    return oracle.run(grid, np.asarray(J_rows, dtype=np.float64), m_rows, Q=Q, table=table)
 
 
 def check_against_oracle(grid, J_rows, m_rows, T_rows, L_rows, H_rows=None, t_tol=T_TOL,
-                         sed_tol=SED_TOL, h_tol=H_TOL):
-    H_ref, T_ref, L_ref = oracle_on_rows(grid, J_rows, m_rows)
+                         sed_tol=SED_TOL, h_tol=H_TOL, Q=None, table=None):
+    H_ref, T_ref, L_ref = oracle_on_rows(grid, J_rows, m_rows, Q=Q, table=table)
+    if Q is not None:  # the GPU's H is the absorbed part only
+        H_ref_abs = H_ref - np.asarray(Q, dtype=np.float64)
+    else:
+        H_ref_abs = H_ref
     res = {"T": t_errors(T_rows, T_ref, H_ref), "SED": sed_errors(L_rows, L_ref, grid.dlam)}
     if H_rows is not None:
-        pos = H_ref > 0
-        rel = np.abs(np.asarray(H_rows, np.float64)[pos] - H_ref[pos]) / H_ref[pos]
+        pos = H_ref_abs > 0
+        rel = np.abs(np.asarray(H_rows, np.float64)[pos] - H_ref_abs[pos]) / H_ref_abs[pos]
         res["H"] = float(rel.max()) if rel.size else 0.0
         assert res["H"] <= h_tol, res
     assert res["T"]["max"] <= t_tol, res

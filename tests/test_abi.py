@@ -64,6 +64,8 @@ def _desc(nl=8, s=2, lam=None, cabs=None, size=None):
     ("cabs_nan", dust.DUST_EINVAL),
     ("size_zero", dust.DUST_EINVAL),
     ("bad_mode", dust.DUST_EINVAL),
+    ("bad_mode3", dust.DUST_EINVAL),
+    ("bad_ltab_linear", dust.DUST_EINVAL),
     ("bad_ltab", dust.DUST_EINVAL),
     ("bad_trange", dust.DUST_EINVAL),
     ("bad_fused_kernels", dust.DUST_EINVAL),
@@ -94,8 +96,12 @@ def test_plan_create_rejects(L, case, expect):
         size = size.copy(); size[1] = 0.0
     if case == "bad_mode":
         opt.mode = 7
+    if case == "bad_mode3":
+        opt.mode = 3
     if case == "bad_ltab":
         opt.ltab_n = 3
+    if case == "bad_ltab_linear":
+        opt.mode, opt.ltab_n = dust.TABLE_LINEAR, 15
     if case == "bad_trange":
         opt.ltab_tmin, opt.ltab_tmax = 100.0, 50.0
     if case == "bad_fused_kernels":
@@ -123,6 +129,10 @@ def test_null_arguments(L):
     assert L.dust_solve_T(nul, 4, nul, 2, nul, 2, nul, nul) == dust.DUST_EINVAL
     assert L.dust_emit_sed(nul, 4, nul, 2, nul, nul, 8, nul) == dust.DUST_EINVAL
     assert L.dust_run_fused(nul, 4, nul, 8, nul, nul, 2, nul, 8, nul, nul) == dust.DUST_EINVAL
+    x = dust.SolveExt(None, 0, 1, 0)
+    assert L.dust_solve_T_ext(nul, 4, nul, 2, ctypes.byref(x), nul, 2, nul, nul) == dust.DUST_EINVAL
+    assert L.dust_run_fused_ext(nul, 4, nul, 8, nul, ctypes.byref(x), nul, 2, nul, 8, nul,
+                                nul) == dust.DUST_EINVAL
     assert L.dust_plan_prepare(nul, nul) == dust.DUST_EINVAL
     assert L.dust_plan_info(nul, nul, nul, nul) == dust.DUST_EINVAL
     assert L.dust_batch_launch(nul, nul) == dust.DUST_EINVAL
@@ -143,3 +153,15 @@ def test_product_package_has_no_oracle_dependency():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.lower(), f
                 assert "dust_ref" not in src, f
+
+
+def test_binding_constants_match_header():
+    """The binding's mode values and counter layout follow include/dust.h."""
+    text = open(os.path.join(ROOT, "include", "dust.h")).read()
+    assert re.search(r"DUST_PLAIN_FP32 = 0", text) and re.search(r"DUST_MIXED = 1", text)
+    assert re.search(r"DUST_TABLE_LINEAR = 2", text)
+    assert (dust.PLAIN, dust.MIXED, dust.TABLE_LINEAR) == (0, 1, 2)
+    body = re.search(r"typedef struct \{(.*?)\} dust_counters;", text, re.S).group(1)
+    assert len(re.findall(r"int64_t\s+n_\w+;", body)) == dust.N_COUNTERS
+    ext = re.search(r"typedef struct \{(.*?)\} dust_solve_ext;", text, re.S).group(1)
+    assert ctypes.sizeof(dust.SolveExt) == 24 and "warm_start" in ext and "ldq" in ext
