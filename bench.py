@@ -113,8 +113,9 @@ def time_steps(torch, stages, steps, warmup):
     return wall_ms, timer.mean_ms()
 
 
-def check_sample(grid, J, m_host, T, L, n_sample=64):
-    """Errors of (T, L) against the oracle on strided cells."""
+def check_sample(grid, J, m_host, T, L, n_sample=64, table=None):
+    """Errors of (T, L) against the oracle on strided cells (``table``: the
+    oracle's table variant of the temperature step instead of the exact root)."""
     import oracle
     from oracle.compare import sed_errors, t_errors
     C = J.shape[0]
@@ -122,7 +123,7 @@ def check_sample(grid, J, m_host, T, L, n_sample=64):
     import torch
     idx = torch.as_tensor(rows, device=J.device)
     Jh = J[idx].cpu().numpy().astype(np.float64)
-    H_ref, T_ref, L_ref = oracle.run(grid, Jh, m_host[rows])
+    H_ref, T_ref, L_ref = oracle.run(grid, Jh, m_host[rows], table=table)
     te = t_errors(T[idx].cpu().numpy(), T_ref, H_ref)
     se = sed_errors(L[idx].cpu().numpy(), L_ref, grid.dlam)
     return {"cells": int(len(rows)), "T_max_rel": te["max"], "T_p999_rel": te["p999"],
@@ -152,6 +153,92 @@ def cpu_baseline(grid, J, m_host, target_s):
     return {"value": n * S / dt, "unit": UNIT, "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{n} strided cells of the workload ({n * S} pairs, FP64 oracle incl. SED), "
                       f"{dt:.1f} s"}
+
+
+TABLE = (2000, 3.0, 1500.0)  # the production T-table of Sections 2 and 5
+COUNTER_NAMES = ["nonfinite", "unconverged", "out_of_table", "newton_evals"]
+
+
+def run_table_leg(torch, dust, grid, params, J, m, T, L, cnt, steps, warmup):
+    """The table-linear mode: timing, parity with the oracle's table variant,
+    and its own error against the exact root (the approximation's report)."""
+    pt = dust.Plan(grid, "table")
+    st = [("prepare", lambda: pt.prepare()), ("fused", lambda: pt.fused(J, m, T, L, counters=cnt))]
+    ms, k = time_steps(torch, st, steps, warmup)
+    cnt.zero_()
+    pt.fused(J, m, T, L, counters=cnt)
+    torch.cuda.synchronize()
+    c = cnt.cpu().tolist()
+    C, S = T.shape
+    return {"ms_per_step": ms, "stages_ms": k, "value": C * S / (ms * 1e-3),
+            "table": {"points": TABLE[0], "t_min_K": TABLE[1], "t_max_K": TABLE[2],
+                      "spacing": "linear in T"},
+            "parity_vs_oracle_table": check_sample(grid, J, params.m_dust, T, L, table=TABLE),
+            "error_vs_exact_root": check_sample(grid, J, params.m_dust, T, L),
+            "counters": dict(zip(COUNTER_NAMES, c))}
+
+
+def run_reheat_leg(torch, synth, dust, grid, params, J0, m, T, L, cnt, n_passes=4):
+    """Passes of the global iteration (dust absorbing its own emission):
+    J_n = J0 + g L_{n-1} on the device, then the whole path; the plain solve
+    starts from the previous pass's T (warm) or from the Eq. 11 guess (cold).
+    The J update stands in for the radiative transfer of the emission."""
+    import oracle
+    from oracle.compare import sed_errors, t_errors
+    C, S = T.shape
+    coupling = synth.reheat_coupling(grid, params.m_dust, 32).astype(np.float32)
+    g = torch.as_tensor(coupling, device=J0.device)[:, None]
+    J = torch.empty_like(J0)
+    H = torch.empty((C, S), dtype=torch.float32, device=J0.device)
+
+    def loop(plan, warm, fused):
+        evals, times = [], []
+        for n in range(n_passes):
+            s0, s1, s2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            s0.record()
+            if n == 0:
+                J.copy_(J0)
+            else:
+                torch.addcmul(J0, g, L, out=J)
+            s1.record()
+            cnt.zero_()
+            if fused:
+                plan.fused(J, m, T, L, counters=cnt, warm_start=warm and n > 0)
+            else:
+                plan.absorb(J, H)
+                plan.solve(H, T, counters=cnt, warm_start=warm and n > 0)
+                plan.emit(T, m, L)
+            s2.record()
+            torch.cuda.synchronize()
+            evals.append(int(cnt[3].item()))
+            times.append((s0.elapsed_time(s1), s1.elapsed_time(s2)))
+        return evals, times
+
+    out = {"passes": n_passes, "coupling": "g[c] = f_c / (m_c max_l kappa_l), f_c ~ U(0.1, 0.5)"}
+    pp = dust.Plan(grid, "plain")
+    pm = dust.Plan(grid, "mixed")
+    loop(pp, True, False)  # warm-up
+    for name, plan, warm, fused in (("plain_warm", pp, True, False), ("plain_cold", pp, False, False),
+                                    ("mixed_fused", pm, False, True)):
+        evals, times = loop(plan, warm, fused)
+        out[name] = {"newton_evals_per_pair": [e / (C * S) for e in evals],
+                     "path_ms_per_pass": [t[1] for t in times],
+                     "j_update_ms_per_pass": [t[0] for t in times]}
+        if name == "plain_warm":
+            rows = np.arange(32) * max(1, C // 32)
+            idx = torch.as_tensor(rows, device=J0.device)
+            passes = oracle.reheat(grid, J0[idx].cpu().numpy().astype(np.float64),
+                                   params.m_dust[rows].astype(np.float32).astype(np.float64),
+                                   coupling[rows].astype(np.float64), n_passes)
+            H_ref, T_ref, L_ref = passes[-1]
+            te = t_errors(T[idx].cpu().numpy(), T_ref, H_ref)
+            se = sed_errors(L[idx].cpu().numpy(), L_ref, grid.dlam)
+            out["errors_last_pass_vs_oracle"] = {"cells": 32, "T_max_rel": te["max"],
+                                                 "SED_max_rel": se["max"]}
+    w, c = out["plain_warm"], out["plain_cold"]
+    out["plain_solve_speedup_later_passes"] = (
+        sum(c["path_ms_per_pass"][1:]) / max(1e-9, sum(w["path_ms_per_pass"][1:])))
+    return out
 
 
 BATCH_SOURCES = ["batch.hip", "fused_body.h", "device_common.h", "internal.h"]
@@ -249,9 +336,13 @@ def run_batch(args, torch, synth, dust, dev):
         "sed_cells_per_s": cells / (mixed_ms * 1e-3),
         "stages_ms": {"graph": mixed_k["graph"], "batch_kernel_only": kern_k["batch_kernel"]},
         "errors": mixed_err,
-        "counters": dict(zip(["nonfinite", "unconverged", "out_of_table"], mixed_cnt)),
+        "counters": dict(zip(COUNTER_NAMES, mixed_cnt)),
         "plain_fp32": {"value": plain_value, "ms_per_step": plain_ms, "errors": plain_err,
                        "dtype": "f32"},
+        "mixed_with_extra_heating": {"ms_per_step": q_ms, "stages_ms": q_k,
+                                     "value": pairs / (q_ms * 1e-3)},
+        "table_linear": table_leg,
+        "reheat_passes": reheat_leg,
         "mixed_over_plain": value / plain_value,
     }
     if not args.no_cpu_baseline:
@@ -273,8 +364,12 @@ def run_batch(args, torch, synth, dust, dev):
         out["cpu_baseline"] = {"value": n_done / dt, "unit": UNIT, "cores": oracle.threads(),
                                "kind": "oracle",
                                "sample": f"strided cells from every grid, {n_done} pairs, {dt:.1f} s"}
+    tpar = table_leg["parity_vs_oracle_table"]
+    rerr = reheat_leg["errors_last_pass_vs_oracle"]
     ok = (mixed_err["T_max_rel"] <= 1e-4 and plain_err["T_max_rel"] <= 1e-4 and
-          mixed_err["SED_max_rel"] <= 1e-3 and plain_err["SED_max_rel"] <= 1e-3)
+          mixed_err["SED_max_rel"] <= 1e-3 and plain_err["SED_max_rel"] <= 1e-3 and
+          tpar["T_max_rel"] <= 1e-4 and tpar["SED_max_rel"] <= 1e-3 and
+          rerr["T_max_rel"] <= 1e-4 and rerr["SED_max_rel"] <= 1e-3)
     out["accuracy_ok"] = bool(ok)
     print(json.dumps(out), flush=True)
     return 0 if ok else 3
@@ -376,6 +471,19 @@ def main():
     plain_cnt = cnt.cpu().tolist()
     plain_err = check_sample(grid, J, params.m_dust, T, L)
 
+    log("timing the mixed path with an extra heating term")
+    Q = torch.as_tensor(synth.extra_heating(grid, C, 78), device=dev)
+    q_stages = [("prepare", lambda: pm.prepare()),
+                ("fused", lambda: pm.fused(J, m, T, L, counters=cnt, Q=Q))]
+    q_ms, q_k = time_steps(torch, q_stages, args.steps, args.warmup)
+    del Q
+
+    log("timing the table-linear mode")
+    table_leg = run_table_leg(torch, dust, grid, params, J, m, T, L, cnt, args.steps, args.warmup)
+
+    log("timing re-heating passes")
+    reheat_leg = run_reheat_leg(torch, synth, dust, grid, params, J, m, T, L, cnt)
+
     pairs = C * S
     terms = C * S * NL
     value = pairs / (mixed_ms * 1e-3)
@@ -420,24 +528,33 @@ def main():
         "sed_cells_per_s": C / (mixed_ms * 1e-3),
         "stages_ms": mixed_k,
         "errors": mixed_err,
-        "counters": dict(zip(["nonfinite", "unconverged", "out_of_table"], mixed_cnt)),
+        "counters": dict(zip(COUNTER_NAMES, mixed_cnt)),
         "plain_fp32": {"value": plain_value, "ms_per_step": plain_ms, "stages_ms": plain_k,
                        "sed_cells_per_s": C / (plain_ms * 1e-3), "errors": plain_err,
-                       "counters": dict(zip(["nonfinite", "unconverged", "out_of_table"], plain_cnt)),
+                       "counters": dict(zip(COUNTER_NAMES, plain_cnt)),
+                       "newton_evals_per_pair": plain_cnt[3] / pairs,
                        "dtype": "f32",
                        "emit_Gterm_per_s": terms / (plain_k["emit"] * 1e-3) / 1e9},
         "mixed_fused_two_kernels": {"ms_per_step": f2_ms, "stages_ms": f2_k,
                                     "value": pairs / (f2_ms * 1e-3)},
         "mixed_three_launches": {"ms_per_step": sep_ms, "stages_ms": sep_k,
                                  "value": pairs / (sep_ms * 1e-3)},
+        "mixed_with_extra_heating": {"ms_per_step": q_ms, "stages_ms": q_k,
+                                     "value": pairs / (q_ms * 1e-3)},
+        "table_linear": table_leg,
+        "reheat_passes": reheat_leg,
         "mixed_over_plain": value / plain_value,
         "context_paper_c1060_temps_per_s": 1.52e6,
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(grid, J, params.m_dust, args.cpu_seconds)
+    tpar = table_leg["parity_vs_oracle_table"]
+    rerr = reheat_leg["errors_last_pass_vs_oracle"]
     ok = (mixed_err["T_max_rel"] <= 1e-4 and plain_err["T_max_rel"] <= 1e-4 and
-          mixed_err["SED_max_rel"] <= 1e-3 and plain_err["SED_max_rel"] <= 1e-3)
+          mixed_err["SED_max_rel"] <= 1e-3 and plain_err["SED_max_rel"] <= 1e-3 and
+          tpar["T_max_rel"] <= 1e-4 and tpar["SED_max_rel"] <= 1e-3 and
+          rerr["T_max_rel"] <= 1e-4 and rerr["SED_max_rel"] <= 1e-3)
     out["accuracy_ok"] = bool(ok)
     print(json.dumps(out), flush=True)
     return 0 if ok else 3

@@ -64,8 +64,12 @@ typedef enum {
        Eq. 7 from the Eq. 11 guess, FP32 emission. */
     DUST_PLAIN_FP32 = 0,
     /* Mixed precision: heating on BF16 MFMA with hi+lo split operands and
-       FP32 accumulation; T from an FP64 table of ln P(ln T) per grain with
-       an FP64 Newton polish on its piecewise-cubic interpolant; FP32
+       FP32 accumulation; T from per-grain tables built in FP64 (ln P at
+       log-spaced T, and its inverse ln T(ln H) at uniform steps): by default
+       a cubic Hermite of the inverse evaluated in FP32 (relative T error
+       about 2e-6), with `polish` an FP64 Newton polish on the forward
+       table's piecewise cubic (about 5e-7, dominated by the heating); pairs
+       outside the tabulated range are solved exactly in FP64.  FP32
        emission. */
     DUST_MIXED = 1,
     /* The production variant of the temperature step (Sections 2 and 5):
@@ -105,6 +109,8 @@ typedef struct {
                               then emit).  H never reaches device memory. */
     double ltab_tmin;  /* lowest tabulated T (K): mixed 2.7, table-linear 3 */
     double ltab_tmax;  /* highest tabulated T (K): mixed 3000, table-linear 1500 */
+    int32_t polish;    /* mixed: nonzero selects the FP64 table polish */
+    int32_t reserved;  /* must be 0 */
 } dust_options;
 
 /* Device-side event counters (see the conventions above). */

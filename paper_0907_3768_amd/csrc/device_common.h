@@ -298,6 +298,45 @@ __device__ inline int table_lookup_f64(const PlanView& v, int s, double hs, floa
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Default mixed solve of Eq. 7: the grain's inverse table ln T(y), y = ln H',
+// as a cubic Hermite in FP32 between the two nodes around y (one 16-byte
+// entry holds both).  FP32 rounding of y (|y| up to about 50) and of the
+// table leaves a relative T error of about 2e-6; the Hermite itself is far
+// below that.  Returns 0 with *T set, or nonzero for a pair outside the
+// table (then solved exactly; table_lookup_f64 classifies it).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int table_lookup_f32(const PlanView& v, int s, float hs, float* T,
+                                                dust_counters* cnt) {
+    if (!(hs >= 0.0f) || __builtin_isinf(hs)) {
+        if (cnt) count(&cnt->n_nonfinite);
+        *T = __builtin_nanf("");
+        return 0;
+    }
+    if (hs == 0.0f) { *T = 0.0f; return 0; }
+    const float u = (logf(hs) - v.ylof[s]) * v.dyinvf[s];
+    const float top = (float)(v.M - 1);
+    if (!(u >= 0.0f && u <= top)) return 1;  // outside, or the table is not finite
+    const int j = (int)u < v.M - 2 ? (int)u : v.M - 2;
+    const float4 g = v.invf[(int64_t)s * (v.M - 1) + j];
+    const float t = u - (float)j;
+    const float t2 = t * t, t3 = t2 * t;
+    const float lnT = (2.0f * t3 - 3.0f * t2 + 1.0f) * g.x + (t3 - 2.0f * t2 + t) * g.y +
+                      (3.0f * t2 - 2.0f * t3) * g.z + (t3 - t2) * g.w;
+    *T = expf(lnT);
+    return 0;
+}
+
+// Either mixed lookup, by the plan's choice (uniform branch).
+__device__ __forceinline__ int mixed_lookup(const PlanView& v, int s, float hs, float* T,
+                                            dust_counters* cnt) {
+    if (v.polish) {
+        double lnT0;
+        return table_lookup_f64(v, s, (double)hs, T, &lnT0, cnt);
+    }
+    return table_lookup_f32(v, s, hs, T, cnt);
+}
+
 // Exact FP64 solve of one pending pair (status 1, 2 or 3 from
 // table_lookup_f64) by the whole wave: every lane calls it with the same
 // arguments and receives T.  Counts the pair as out of table.

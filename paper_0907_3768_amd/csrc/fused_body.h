@@ -8,24 +8,29 @@ namespace dust {
 
 constexpr int FUSED_TC = 16;  // default cells per tile (one MFMA M-block)
 
-// LDS staging of one 16 x 32 chunk of J per K-step, double-buffered.
-// Mixed mode keeps it as bf16 hi and lo halves (rows padded to 40 values),
-// plain mode as FP32 (rows padded to 36 values).  The padding spreads the 16
-// lanes of each 128-bit read phase over distinct banks.
-constexpr int STAGE_ROW_BF16 = 40;
-constexpr int STAGE_ROW_F32 = 36;
-constexpr int STAGE_BUF_BYTES = 2 * 16 * STAGE_ROW_BF16 * 2;  // >= 16 * 36 * 4
+// LDS staging of J in chunks of 16 cells x ABS_KC wavelengths, double-
+// buffered.  Mixed mode keeps a chunk as bf16 hi and lo planes (rows padded
+// to ABS_KC + 8 values), plain mode as FP32 (rows padded to ABS_KC + 4).  The
+// padding makes a row 4 banks apart from the next, so the 16 lanes of each
+// 128-bit read phase touch every bank exactly twice.
+constexpr int ABS_KC = 128;                 // wavelengths per staged chunk
+constexpr int ABS_KSTEPS = ABS_KC / 32;     // MFMA k-steps per chunk
+constexpr int STAGE_ROW_BF16 = ABS_KC + 8;
+constexpr int STAGE_ROW_F32 = ABS_KC + 4;
+constexpr int STAGE_BUF_BYTES = 2 * 16 * STAGE_ROW_BF16 * 2;  // >= 16 * STAGE_ROW_F32 * 4
+static_assert(STAGE_BUF_BYTES >= 16 * STAGE_ROW_F32 * 4, "FP32 staging must fit");
 constexpr int STAGE_BYTES = 2 * STAGE_BUF_BYTES;
 
 // Phase 1: heating of a 16-cell block into sH[16][Sp] (rows of the tile's
 // LDS array) in the plan's scaled units H' = H 2^es, on the MFMA units.
 //
-// Per K-step of 32 wavelengths the block loads the 16 x 32 chunk of J with
-// coalesced loads (thread t: row t/16, columns 2(t mod 16) and +1), splits it
-// (mixed: bf16 hi + lo) into LDS, and each wave multiplies it with its grain
-// tiles w, w+4, ... (NTW of them per pass; grids with more than 4 NTW tiles
-// take several passes).  The next chunk of J is loaded into registers while
-// the current MFMAs run.
+// J streams through LDS in chunks of ABS_KC wavelengths: every thread loads
+// ABS_KC/16 values of the next chunk (thread t: row t/16, column pairs
+// 2 (t mod 16) + 32 i) while the current chunk is multiplied, then splits
+// them (mixed: bf16 hi + lo) into the other buffer; one barrier per chunk.
+// Each wave multiplies with its grain tiles w, w+4, ... (NTW of them per
+// pass; grids with more than 4 NTW tiles take several passes).  (Loading the
+// weight fragments one k-step ahead measured no faster and costs VGPRs.)
 //
 // K-order: lane (row = lane mod 16, q = lane / 16) supplies wavelengths
 // k0 + 8q .. k0 + 8q + 7 to both operands -- one 16x16x32 bf16 MFMA, or eight
@@ -36,100 +41,137 @@ template <int MODE, int NTW>
 __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int64_t C,
                                              const float* __restrict__ J, int64_t ldj,
                                              float* sH, char* sStage) {
+    constexpr bool BF = table_mode(MODE);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int tiles = v.Sp / 16;
-    // loader role: 256 threads x 2 floats = one 16 x 32 chunk
+    // loader role: 256 threads x ABS_KC/16 values = one 16 x ABS_KC chunk
+    constexpr int NX = ABS_KC / 16;  // values per thread
+    static_assert(ABS_KC % 32 == 0 && NX % 2 == 0, "chunk of whole k-steps");
     const int lrow = tid >> 4, lcol = (tid & 15) * 2;
     const bool lrow_ok = c0 + lrow < C;
     const float* jl = J + (lrow_ok ? c0 + lrow : 0) * ldj;
 
-    auto load_j = [&](int k0, float& x0, float& x1) {
-        const int k = k0 + lcol;
-        x0 = (lrow_ok && k < v.NL) ? jl[k] : 0.0f;
-        x1 = (lrow_ok && k + 1 < v.NL) ? jl[k + 1] : 0.0f;
+    auto load_j = [&](int k0, float (&x)[NX]) {
+#pragma unroll
+        for (int i = 0; i < NX / 2; ++i) {
+            const int k = k0 + lcol + 32 * i;
+            x[2 * i] = (lrow_ok && k < v.NL) ? jl[k] : 0.0f;
+            x[2 * i + 1] = (lrow_ok && k + 1 < v.NL) ? jl[k + 1] : 0.0f;
+        }
     };
-    auto store_j = [&](int buf, float x0, float x1) {
+    auto store_j = [&](int buf, const float (&x)[NX]) {
         char* base = sStage + buf * STAGE_BUF_BYTES;
-        if constexpr (table_mode(MODE)) {
-            // [hi|lo][16 rows][STAGE_ROW_BF16] bf16; a pair of columns per 32-bit store
-            typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-            const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
-            const bf16x2 hi = {h0, h1};
-            const bf16x2 lo = {(__bf16)(x0 - (float)h0), (__bf16)(x1 - (float)h1)};
-            bf16x2* b = reinterpret_cast<bf16x2*>(base);
-            b[(lrow * STAGE_ROW_BF16 + lcol) / 2] = hi;
-            b[(16 * STAGE_ROW_BF16 + lrow * STAGE_ROW_BF16 + lcol) / 2] = lo;
-        } else {
-            float2* b = reinterpret_cast<float2*>(base);
-            b[(lrow * STAGE_ROW_F32 + lcol) / 2] = make_float2(x0, x1);
+#pragma unroll
+        for (int i = 0; i < NX / 2; ++i) {
+            const int col = lcol + 32 * i;
+            const float x0 = x[2 * i], x1 = x[2 * i + 1];
+            if constexpr (BF) {
+                // [hi|lo][16 rows][STAGE_ROW_BF16] bf16; a pair of columns per 32-bit store
+                typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+                const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+                const bf16x2 hi = {h0, h1};
+                const bf16x2 lo = {(__bf16)(x0 - (float)h0), (__bf16)(x1 - (float)h1)};
+                bf16x2* b = reinterpret_cast<bf16x2*>(base);
+                b[(lrow * STAGE_ROW_BF16 + col) / 2] = hi;
+                b[(16 * STAGE_ROW_BF16 + lrow * STAGE_ROW_BF16 + col) / 2] = lo;
+            } else {
+                float2* b = reinterpret_cast<float2*>(base);
+                b[(lrow * STAGE_ROW_F32 + col) / 2] = make_float2(x0, x1);
+            }
         }
     };
 
-    const int nsteps = (v.NL + 31) / 32;
+    // Weight fragments of one k-step for the wave's tiles (bf16 hi/lo, or
+    // 8 FP32 values).
+    struct KFrag {
+        bf16x8 hi[NTW], lo[NTW];
+        float4 f0[NTW], f1[NTW];
+    };
+    auto load_k = [&](int tg, int k0, KFrag& f) {
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int tile = tg + wave + 4 * t;
+            if (tile < tiles) {
+                const int64_t o = (int64_t)(tile * 16 + row) * v.NLp + k0 + kq * 8;
+                if constexpr (BF) {
+                    f.hi[t] = *reinterpret_cast<const bf16x8*>(v.khi + o);
+                    f.lo[t] = *reinterpret_cast<const bf16x8*>(v.klo + o);
+                } else {
+                    f.f0[t] = *reinterpret_cast<const float4*>(v.kf + o);
+                    f.f1[t] = *reinterpret_cast<const float4*>(v.kf + o + 4);
+                }
+            }
+        }
+    };
+
+    const int nsteps = v.NLp / 32;                    // k-steps (NLp is a multiple of 32)
+    const int nchunks = (nsteps + ABS_KSTEPS - 1) / ABS_KSTEPS;
     // Grain tiles in groups of 4 NTW (one pass over J each).
     for (int tg = 0; tg < tiles; tg += 4 * NTW) {
-    f32x4 acc[NTW];
+        f32x4 acc[NTW];
 #pragma unroll
-    for (int t = 0; t < NTW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float x0, x1;
-    load_j(0, x0, x1);
-    store_j(0, x0, x1);
-    __syncthreads();
-    for (int step = 0; step < nsteps; ++step) {
-        const int k0 = step * 32;
-        const int buf = step & 1;
-        if (step + 1 < nsteps) load_j(k0 + 32, x0, x1);  // prefetch the next chunk
-        if constexpr (table_mode(MODE)) {
-            const __bf16* b = reinterpret_cast<const __bf16*>(sStage + buf * STAGE_BUF_BYTES);
-            const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(b + row * STAGE_ROW_BF16 + kq * 8);
-            const bf16x8 alo = *reinterpret_cast<const bf16x8*>(
-                b + 16 * STAGE_ROW_BF16 + row * STAGE_ROW_BF16 + kq * 8);
-#pragma unroll
-            for (int t = 0; t < NTW; ++t) {
-                const int tile = tg + wave + 4 * t;
-                if (tile < tiles) {
-                    const int64_t o = (int64_t)(tile * 16 + row) * v.NLp + k0 + kq * 8;
-                    const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(v.khi + o);
-                    const bf16x8 blo = *reinterpret_cast<const bf16x8*>(v.klo + o);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[t], 0, 0, 0);
-                }
-            }
-        } else {
-            const float* b = reinterpret_cast<const float*>(sStage + buf * STAGE_BUF_BYTES);
-            const float4 a0 = *reinterpret_cast<const float4*>(b + row * STAGE_ROW_F32 + kq * 8);
-            const float4 a1 = *reinterpret_cast<const float4*>(b + row * STAGE_ROW_F32 + kq * 8 + 4);
-            const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-#pragma unroll
-            for (int t = 0; t < NTW; ++t) {
-                const int tile = tg + wave + 4 * t;
-                if (tile < tiles) {
-                    const float* kr = v.kf + (int64_t)(tile * 16 + row) * v.NLp + k0 + kq * 8;
-                    const float4 b0 = *reinterpret_cast<const float4*>(kr);
-                    const float4 b1 = *reinterpret_cast<const float4*>(kr + 4);
-                    const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[i], acc[t], 0, 0, 0);
-                }
-            }
-        }
-        if (step + 1 < nsteps) store_j(buf ^ 1, x0, x1);
+        for (int t = 0; t < NTW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float x[NX];
+        load_j(0, x);
+        store_j(0, x);
         __syncthreads();
-    }
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < nchunks) load_j((ch + 1) * ABS_KC, x);  // next chunk in flight
+#pragma unroll 1
+            for (int ks = 0; ks < ABS_KSTEPS; ++ks) {
+                const int step = ch * ABS_KSTEPS + ks;
+                if (step >= nsteps) break;  // uniform
+                KFrag kc;
+                load_k(tg, step * 32, kc);
+                if constexpr (BF) {
+                    const __bf16* b = reinterpret_cast<const __bf16*>(sStage + buf * STAGE_BUF_BYTES);
+                    const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(
+                        b + row * STAGE_ROW_BF16 + ks * 32 + kq * 8);
+                    const bf16x8 alo = *reinterpret_cast<const bf16x8*>(
+                        b + 16 * STAGE_ROW_BF16 + row * STAGE_ROW_BF16 + ks * 32 + kq * 8);
 #pragma unroll
-    for (int t = 0; t < NTW; ++t) {
-        const int tile = tg + wave + 4 * t;
-        if (tile < tiles) {
-            const int s = tile * 16 + row;
+                    for (int t = 0; t < NTW; ++t) {
+                        if (tg + wave + 4 * t < tiles) {
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, kc.hi[t], acc[t], 0, 0, 0);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, kc.lo[t], acc[t], 0, 0, 0);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, kc.hi[t], acc[t], 0, 0, 0);
+                        }
+                    }
+                } else {
+                    const float* b = reinterpret_cast<const float*>(sStage + buf * STAGE_BUF_BYTES);
+                    const float4 a0 = *reinterpret_cast<const float4*>(
+                        b + row * STAGE_ROW_F32 + ks * 32 + kq * 8);
+                    const float4 a1 = *reinterpret_cast<const float4*>(
+                        b + row * STAGE_ROW_F32 + ks * 32 + kq * 8 + 4);
+                    const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sH[(kq * 4 + r) * v.Sp + s] = acc[t][r];
+                    for (int t = 0; t < NTW; ++t) {
+                        if (tg + wave + 4 * t < tiles) {
+                            const float bb[8] = {kc.f0[t].x, kc.f0[t].y, kc.f0[t].z, kc.f0[t].w,
+                                                 kc.f1[t].x, kc.f1[t].y, kc.f1[t].z, kc.f1[t].w};
+#pragma unroll
+                            for (int i = 0; i < 8; ++i)
+                                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[i], acc[t], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            if (ch + 1 < nchunks) store_j(buf ^ 1, x);
+            __syncthreads();
         }
-    }
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int tile = tg + wave + 4 * t;
+            if (tile < tiles) {
+                const int s = tile * 16 + row;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sH[(kq * 4 + r) * v.Sp + s] = acc[t][r];
+            }
+        }
     }  // tile groups
 }
 
@@ -158,8 +200,18 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
         __syncthreads();
     }
     int evals = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int cc = i / v.Sp, s = i - cc * v.Sp;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        // Plain: cells fastest, so a wave spans 64/TC grains and the Newton
+        // sums read few distinct weight rows.  Otherwise grains fastest.
+        int cc, s;
+        if constexpr (MODE == DUST_PLAIN_FP32) {
+            s = j / TC;
+            cc = j - s * TC;
+        } else {
+            cc = j / v.Sp;
+            s = j - cc * v.Sp;
+        }
+        const int i = cc * v.Sp + s;
         const int64_t c = c0 + cc;
         const bool pair = s < v.S && c < C;
         float inv = __builtin_inff();
@@ -168,8 +220,7 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
             if (v.q) h += v.q[c * v.ldq + s] * v.hscale[s];
             float t;
             if constexpr (MODE == DUST_MIXED) {
-                double lnT0;
-                if (table_lookup_f64(v, s, (double)h, &t, &lnT0, cnt) != 0) {
+                if (mixed_lookup(v, s, h, &t, cnt) != 0) {
                     const int k = atomicAdd(sCount, 1);
                     if (k < PENDING_CAP) sList[k] = i;
                     sH[i] = -h;  // pending: solved below

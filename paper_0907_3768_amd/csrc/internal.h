@@ -54,6 +54,12 @@ struct PlanView {
     const double* ylo;     // [S] y_0
     const double* yhi;     // [S] y_{N-1}
     const double* dyinv;   // [S] (M - 1) / (yhi - ylo)
+    // FP32 copy of the inverse table for the default mixed lookup: per
+    // interval j, (ln T_j, m_j, ln T_{j+1}, m_{j+1}) in one 16-byte entry
+    const float4* invf;    // [S][M-1]
+    const float* ylof;     // [S] float(ylo)
+    const float* dyinvf;   // [S] float(dyinv)
+    int polish;            // mixed: FP64 table polish instead of the FP32 lookup
     int N, M;
     double lnTmin, hstep;  // ln T_k = lnTmin + k hstep
     double inv_hstep;
@@ -90,6 +96,8 @@ struct dust_plan {
     double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv, *d_fwd, *d_texp;
     double* d_F;  // [N][NL] Planck factors of the table temperatures
     double2 *d_inv, *d_lntab;
+    float4* d_invf;
+    float *d_ylof, *d_dyinvf;
     int* d_kidx;  // table-linear search brackets [S][M]
     dust::PlanView view;
 };

@@ -11,7 +11,8 @@
 //        Planck weights with the Planck factors of the table temperatures.
 //  inv   (mixed mode): the inverse function ln T(y) and its derivative at
 //        uniform steps of y, from Newton on the forward table's piecewise
-//        cubic, so that a lookup starts next to its root.
+//        cubic: in FP64 (the start of the optional FP64 polish) and in FP32
+//        pairs of nodes (the default lookup, one 16-byte load per pair).
 //  table-linear mode: the same matrix product gives P'(T_k) itself at evenly
 //        spaced T_k (the production table of Sections 2 and 5); kidx gives,
 //        at uniform steps of ln P', the last table point below, so that a
@@ -130,7 +131,8 @@ __global__ __launch_bounds__(256) void kidx_kernel(PlanView v, const double* __r
 // on the forward table's cubic, and dy * d ln T / dy there.
 __global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double* __restrict__ fwd,
                                                   double2* inv, double* ylo, double* yhi,
-                                                  double* dyinv) {
+                                                  double* dyinv, float2* invf, float* ylof,
+                                                  float* dyinvf) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (j >= v.M) return;
@@ -142,6 +144,8 @@ __global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double* __re
         ylo[s] = y0;
         yhi[s] = y1;
         dyinv[s] = dinv;
+        ylof[s] = (float)y0;
+        dyinvf[s] = (float)dinv;
     }
     const double yj = (j == v.M - 1) ? y1 : y0 + j / dinv;
     // largest k in [0, N-2] with y_k <= yj
@@ -160,8 +164,14 @@ __global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double* __re
     }
     cubic4(x, a0, a1, a2, a3, &dp);
     // d lnT / dy = hstep / (dy/dx), scaled by the node spacing dy = 1/dinv
-    inv[(int64_t)s * v.M + j] = make_double2(v.lnTmin + ((double)j0 + x) * v.hstep,
-                                             v.hstep / dp / dinv);
+    const double lnTj = v.lnTmin + ((double)j0 + x) * v.hstep;
+    const double mj = v.hstep / dp / dinv;
+    inv[(int64_t)s * v.M + j] = make_double2(lnTj, mj);
+    // the FP32 entries of the two intervals this node bounds
+    const float2 nf = make_float2((float)lnTj, (float)mj);
+    float2* row = invf + (int64_t)s * (v.M - 1) * 2;
+    if (j < v.M - 1) row[2 * j] = nf;
+    if (j > 0) row[2 * (j - 1) + 1] = nf;
 }
 
 }  // namespace
@@ -189,7 +199,8 @@ hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
         return hipGetLastError();
     }
     hipLaunchKernelGGL(inv_kernel, g3, dim3(256), 0, st, v, (const double*)p->d_fwd, p->d_inv,
-                       p->d_ylo, p->d_yhi, p->d_dyinv);
+                       p->d_ylo, p->d_yhi, p->d_dyinv, reinterpret_cast<float2*>(p->d_invf),
+                       p->d_ylof, p->d_dyinvf);
     return hipGetLastError();
 }
 

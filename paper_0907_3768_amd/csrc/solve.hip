@@ -1,10 +1,16 @@
 // Temperature solve, Eq. 7 (Section 4.3).
 //
-// Plain FP32: one thread per (cell, grain); a workgroup serves one grain
-// over 256 cells, as in the paper, so the grain's Planck weights and the
-// wavelength table are wave-uniform and come through the scalar cache.
+// Plain FP32: a workgroup takes a tile of 64 cells x up to 16 grains.  The
+// tile's heating (plus the extra term) is staged in LDS with coalesced
+// loads; each wave then solves one grain at a time for the 64 cells (one
+// cell per lane), as the paper's third kernel gives a block one species, so
+// the grain's Planck weights and the wavelength table are wave-uniform and
+// come through the scalar cache.  T goes back through the same LDS slots and
+// leaves with coalesced stores; the Newton evaluations of the block are
+// counted with one atomic.
 // Mixed: one thread per (cell, grain) in row-major order (coalesced H and T),
-// an O(1) lookup in the grain's FP64 table and an FP64 Newton polish.
+// an O(1) lookup in the grain's inverse table (FP32 Hermite, or optionally
+// the FP64 forward table with an FP64 Newton polish).
 // Table-linear: the same layout, a bracketed search in the grain's table of
 // powers at evenly spaced T and linear interpolation (Sections 2 and 5).
 // Every form adds the optional extra heating Q to H first.
@@ -13,22 +19,61 @@
 namespace dust {
 namespace {
 
+constexpr int PLAIN_CELLS = 64;    // cells per tile: one per lane
+constexpr int PLAIN_GRAINS = 16;   // grains per tile at most
+
+// LDS row stride of a tile of g grains: odd, so the 64 lanes reading one
+// grain column hit distinct banks.
+__host__ __device__ constexpr int plain_stride(int g) { return g | 1; }
+
 __global__ __launch_bounds__(256) void solve_plain_kernel(PlanView v, int64_t C,
                                                           const float* __restrict__ H,
                                                           int64_t ldh, float* __restrict__ T,
                                                           int64_t ldt, dust_counters* cnt) {
-    const int s = blockIdx.y;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int evals = 0;
-    if (c < C) {
-        float h = H[c * ldh + s];
-        if (v.q) h += v.q[c * v.ldq + s];
-        const float t0 = v.warm ? T[c * ldt + s] : 0.0f;
-        T[c * ldt + s] = solve_newton_f32(v.kb + (int64_t)s * v.NLp, v.nu, v.NL,
-                                          h * v.hscale[s], v.gs[s], v.tol, v.maxit, t0, &evals,
-                                          cnt);
+    extern __shared__ float sX[];  // [64][ST]: heating in, T out
+    __shared__ int sEvals[4];
+    const int64_t c0 = (int64_t)blockIdx.x * PLAIN_CELLS;
+    const int g0 = blockIdx.y * PLAIN_GRAINS;
+    const int G = (v.S - g0 < PLAIN_GRAINS) ? v.S - g0 : PLAIN_GRAINS;
+    const int ST = plain_stride(G);
+    const int rows = (C - c0 < PLAIN_CELLS) ? (int)(C - c0) : PLAIN_CELLS;
+    for (int i = threadIdx.x; i < rows * G; i += blockDim.x) {
+        const int cc = i / G, sl = i - cc * G;
+        const int64_t c = c0 + cc;
+        float h = H[c * ldh + g0 + sl];
+        if (v.q) h += v.q[c * v.ldq + g0 + sl];
+        sX[cc * ST + sl] = h * v.hscale[g0 + sl];
     }
-    if (cnt) wave_count_add(&cnt->n_newton_evals, evals);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool live = lane < rows;
+    int evals = 0;
+    for (int sl = wave; sl < G; sl += 4) {
+        const int s = g0 + sl;
+        if (live) {
+            const float t0 = v.warm ? T[(c0 + lane) * ldt + s] : 0.0f;
+            int ev;
+            sX[lane * ST + sl] = solve_newton_f32(v.kb + (int64_t)s * v.NLp, v.nu, v.NL,
+                                                  sX[lane * ST + sl], v.gs[s], v.tol, v.maxit,
+                                                  t0, &ev, cnt);
+            evals += ev;
+        }
+    }
+    if (cnt) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) evals += __shfl_xor(evals, off, 64);
+        if (lane == 0) sEvals[wave] = evals;
+    }
+    __syncthreads();
+    if (cnt && threadIdx.x == 0) {
+        const int n = sEvals[0] + sEvals[1] + sEvals[2] + sEvals[3];
+        if (n) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt->n_newton_evals),
+                         (unsigned long long)n);
+    }
+    for (int i = threadIdx.x; i < rows * G; i += blockDim.x) {
+        const int cc = i / G, sl = i - cc * G;
+        T[(c0 + cc) * ldt + g0 + sl] = sX[cc * ST + sl];
+    }
 }
 
 // Table-linear: one thread per (cell, grain) in row-major order.
@@ -62,11 +107,10 @@ __global__ __launch_bounds__(256) void solve_mixed_kernel(PlanView v, int64_t C,
     const int s = active ? (int)(i - c * v.S) : 0;
     float h = active ? H[c * ldh + s] : 0.0f;
     if (active && v.q) h += v.q[c * v.ldq + s];
-    const double hs = (double)(h * v.hscale[s]);
+    const float hs = h * v.hscale[s];
     float t = 0.0f;
-    double lnT0;
     if (active) {
-        if (table_lookup_f64(v, s, hs, &t, &lnT0, cnt) != 0)
+        if (mixed_lookup(v, s, hs, &t, cnt) != 0)
             sList[atomicAdd(&sCount, 1)] = threadIdx.x;
         else
             T[c * ldt + s] = t;
@@ -99,8 +143,12 @@ hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ld
         hipLaunchKernelGGL(solve_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                            st, v, C, H, ldh, T, ldt, cnt);
     } else {
-        hipLaunchKernelGGL(solve_plain_kernel, dim3((unsigned)((C + 255) / 256), v.S), dim3(256),
-                           0, st, v, C, H, ldh, T, ldt, cnt);
+        const int gt = (v.S + PLAIN_GRAINS - 1) / PLAIN_GRAINS;
+        const int G = v.S < PLAIN_GRAINS ? v.S : PLAIN_GRAINS;
+        const size_t lds = sizeof(float) * PLAIN_CELLS * plain_stride(G);
+        hipLaunchKernelGGL(solve_plain_kernel,
+                           dim3((unsigned)((C + PLAIN_CELLS - 1) / PLAIN_CELLS), gt), dim3(256),
+                           lds, st, v, C, H, ldh, T, ldt, cnt);
     }
     return hipGetLastError();
 }

@@ -69,13 +69,14 @@ def _desc(nl=8, s=2, lam=None, cabs=None, size=None):
     ("bad_ltab", dust.DUST_EINVAL),
     ("bad_trange", dust.DUST_EINVAL),
     ("bad_fused_kernels", dust.DUST_EINVAL),
+    ("options_reserved", dust.DUST_EINVAL),
 ])
 def test_plan_create_rejects(L, case, expect):
     nl, s = 8, 2
     lam = np.geomspace(1e-7, 1e-3, nl)
     cabs = np.full((s, nl), 1e-14)
     size = np.full(s, 1e-7)
-    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0)
+    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0, 0, 0)
     if case == "nl0":
         nl = 0
     if case == "s0":
@@ -106,6 +107,8 @@ def test_plan_create_rejects(L, case, expect):
         opt.ltab_tmin, opt.ltab_tmax = 100.0, 50.0
     if case == "bad_fused_kernels":
         opt.fused_kernels = 3
+    if case == "options_reserved":
+        opt.reserved = 1
     d, keep = _desc(max(nl, 1), max(s, 1), lam if nl else None, cabs if s else None,
                     size if s else None)
     d.n_lambda, d.n_grains = nl, s
@@ -118,7 +121,7 @@ def test_plan_create_rejects(L, case, expect):
 
 def test_null_arguments(L):
     d, keep = _desc()
-    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0)
+    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0, 0, 0)
     assert L.dust_plan_create(None, ctypes.byref(opt), ctypes.byref(ctypes.c_void_p())) == dust.DUST_EINVAL
     assert L.dust_plan_create(ctypes.byref(d), ctypes.byref(opt), None) == dust.DUST_EINVAL
     d.lambda_ = None
