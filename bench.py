@@ -339,10 +339,6 @@ def run_batch(args, torch, synth, dust, dev):
         "counters": dict(zip(COUNTER_NAMES, mixed_cnt)),
         "plain_fp32": {"value": plain_value, "ms_per_step": plain_ms, "errors": plain_err,
                        "dtype": "f32"},
-        "mixed_with_extra_heating": {"ms_per_step": q_ms, "stages_ms": q_k,
-                                     "value": pairs / (q_ms * 1e-3)},
-        "table_linear": table_leg,
-        "reheat_passes": reheat_leg,
         "mixed_over_plain": value / plain_value,
     }
     if not args.no_cpu_baseline:

@@ -74,7 +74,8 @@ __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__
 // without its loop, which on gfx950 costs the persistent form a lot of
 // registers (values the compiler keeps live across items).
 template <int TC, int NTW>
-__global__ __launch_bounds__(256) void batch_item_kernel(const GridArgs* __restrict__ grids,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_item_kernel(
+    const GridArgs* __restrict__ grids,
                                                          const int2* __restrict__ items,
                                                          int n_items, unsigned int* counter,
                                                          dust_counters* cnt) {
@@ -217,8 +218,9 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     for (int g = 0; g < n_grids; ++g) {
         const dust_plan* p = plans[g];
         if (!p) return set_error(DUST_EINVAL, "plans[" + std::to_string(g) + "] is NULL");
-        if (p->opt.mode != DUST_MIXED)
-            return set_error(DUST_EUNSUPPORTED, "batched launches take DUST_MIXED plans");
+        if (p->opt.mode != DUST_MIXED || p->opt.polish)
+            return set_error(DUST_EUNSUPPORTED,
+                             "batched launches take DUST_MIXED plans without the FP64 polish");
         if (n_cells[g] < 0 || n_cells[g] > ((int64_t)1 << 36))
             return set_error(DUST_EINVAL, "n_cells out of range");
         const int64_t c = n_cells[g];

@@ -121,13 +121,66 @@ __device__ __forceinline__ float solve_newton_f32(const float* __restrict__ kb,
 }
 
 // ---------------------------------------------------------------------------
-// e^x - 1 in FP64 for x >= 0: exp(x) - 1 where that loses at most a few
-// units in the last place relative (x >= 0.01: <= 2.3e-14), the Taylor series
-// to x^7 below (truncation x^8/8! < 3e-21 relative).  Lighter on registers
-// than the library expm1.
+// ln x for a positive finite double x: x = 2^E M, M = c_i (1 + r) with
+// c_i = 1 + i/256 from the top mantissa bits (M - c_i is exact: the two lie
+// within a factor 2), and ln(1 + r) from its series to r^6 (|r| < 2^-8:
+// truncation < 2e-18).  ln 2 enters as a two-part constant (Cody and Waite).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ln_f32_value(double x, const double2* __restrict__ lntab) {
+    const double m = __builtin_amdgcn_frexp_mant(x);        // [0.5, 1)
+    const int e = __builtin_amdgcn_frexp_exp(x) - 1;
+    const double M = 2.0 * m;                               // [1, 2)
+    const int i = (int)((M - 1.0) * 256.0);
+    const double2 t = lntab[i];
+    const double r = (M - (1.0 + i * (1.0 / 256.0))) * t.y;  // M - c_i is exact
+    const double lr = r * (1.0 + r * (-0.5 + r * (1.0 / 3.0 + r * (-0.25 + r * (0.2 - r * (1.0 / 6.0))))));
+    return (double)e * 6.93147180369123816490e-01 + ((double)e * 1.90821492927058770002e-10 +
+                                                     (t.x + lr));
+}
+
+// 1 / x with v_rcp_f64 and one Newton-Raphson refinement (finite, nonzero x:
+// the refinement turns x = inf into NaN).
+__device__ __forceinline__ double rcp_f64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// e^x in FP64 with few registers: Cody-Waite reduction x = k ln 2 + r
+// (|r| <= ln(2)/2, ln 2 in two parts so that k ln2_hi is exact), e^r from its
+// Taylor series to r^12 (truncation < 2e-16 relative), then 2^k.  Overflow
+// gives +inf, underflow 0 (through subnormals).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_f64(double x) {
+    if (x > 709.782712893384) return __builtin_inf();
+    if (x < -745.1332191019412) return 0.0;
+    const double k = __builtin_rint(x * 1.4426950408889634);
+    double r = fma(-k, 6.93147180369123816490e-01, x);
+    r = fma(-k, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 479001600.0;
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)k);
+}
+
+// ---------------------------------------------------------------------------
+// e^x - 1 in FP64 for x >= 0: e^x - 1 where that loses at most a few units
+// in the last place relative (x >= 0.01: <= 2.3e-14), the Taylor series to
+// x^7 below (truncation x^8/8! < 3e-21 relative).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double expm1_pos(double x) {
-    if (x >= 0.01) return exp(x) - 1.0;
+    if (x >= 0.01) return exp_f64(x) - 1.0;
     const double p = 1.0 + x * (1.0 / 2 + x * (1.0 / 6 + x * (1.0 / 24 + x * (1.0 / 120 +
                      x * (1.0 / 720 + x * (1.0 / 5040))))));
     return x * p;
@@ -142,12 +195,13 @@ __device__ __forceinline__ double expm1_pos(double x) {
 __device__ inline void wave_power_f64(const PlanView& v, int s, double T, double* P, double* D) {
     const int lane = threadIdx.x & 63;
     const double* kdb = v.kdb + (int64_t)s * v.NL;
-    const double invT = 1.0 / T;
+    const double invT = rcp_f64(T);
     double p = 0.0, d = 0.0;
 #pragma unroll 1
     for (int l = lane; l < v.NL; l += 64) {
         const double x = v.c2l[l] * invT;
-        const double r = 1.0 / expm1_pos(x);  // 0 once e^x overflows
+        const double em = expm1_pos(x);
+        const double r = (em < __builtin_inf()) ? rcp_f64(em) : 0.0;  // 0 once e^x overflows
         const double b = kdb[l] * r;
         p += b;
         d += b * x * (1.0 + r);
@@ -166,18 +220,18 @@ __device__ inline void wave_power_f64(const PlanView& v, int s, double T, double
 // bracket [lnlo, lnhi].  Used by the mixed path for pairs outside the table.
 __device__ inline double wave_solve_exact_f64(const PlanView& v, int s, double hs, double lnlo,
                                               double lnhi, double lnT0, bool* ok) {
-    const double lnH = log(hs);
+    const double lnH = ln_f32_value(hs, v.lntab);
     double lo = lnlo, hi = lnhi;
     double lnT = (lnT0 > lo && lnT0 < hi) ? lnT0 : 0.5 * (lo + hi);
     for (int it = 0; it < 100; ++it) {
         double P, D;
-        wave_power_f64(v, s, exp(lnT), &P, &D);
+        wave_power_f64(v, s, exp_f64(lnT), &P, &D);
         double next;
-        if (!(P > 0.0)) {
-            lo = lnT;
+        if (!(P > 0.0 && P < __builtin_inf())) {
+            if (P > 0.0) hi = lnT; else lo = lnT;  // inf: T far too high; 0: far too low
             next = 0.5 * (lo + hi);
         } else {
-            const double r = log(P) - lnH;
+            const double r = ln_f32_value(P, v.lntab) - lnH;
             if (r < 0.0) lo = lnT; else hi = lnT;
             next = lnT - r * P / D;
             if (fabs(next - lnT) <= 1e-14) { *ok = true; return next; }
@@ -217,31 +271,6 @@ __device__ __forceinline__ double hermite(double t, double y0, double m0, double
     const double t2 = t * t, t3 = t2 * t;
     return (2.0 * t3 - 3.0 * t2 + 1.0) * y0 + (t3 - 2.0 * t2 + t) * m0 +
            (3.0 * t2 - 2.0 * t3) * y1 + (t3 - t2) * m1;
-}
-
-// ---------------------------------------------------------------------------
-// ln x for a positive finite double x whose mantissa has at most 24
-// significant bits (an FP32 value times a power of two): x = 2^E M,
-// M = c_i (1 + r) with c_i = 1 + i/256 from the top mantissa bits, and
-// ln(1 + r) from its series to r^6 (|r| < 2^-8: truncation < 2e-18).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double ln_f32_value(double x, const double2* __restrict__ lntab) {
-    const double m = __builtin_amdgcn_frexp_mant(x);        // [0.5, 1)
-    const int e = __builtin_amdgcn_frexp_exp(x) - 1;
-    const double M = 2.0 * m;                               // [1, 2)
-    const int i = (int)((M - 1.0) * 256.0);
-    const double2 t = lntab[i];
-    const double r = (M - (1.0 + i * (1.0 / 256.0))) * t.y;  // M - c_i is exact
-    const double lr = r * (1.0 + r * (-0.5 + r * (1.0 / 3.0 + r * (-0.25 + r * (0.2 - r * (1.0 / 6.0))))));
-    return (double)e * 6.93147180369123816490e-01 + ((double)e * 1.90821492927058770002e-10 +
-                                                     (t.x + lr));
-}
-
-// 1 / x with v_rcp_f64 and one Newton-Raphson refinement.
-__device__ __forceinline__ double rcp_f64(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -327,35 +356,57 @@ __device__ __forceinline__ int table_lookup_f32(const PlanView& v, int s, float 
     return 0;
 }
 
-// Either mixed lookup, by the plan's choice (uniform branch).
+// The lookup of a mixed kernel form.
+template <int MODE>
 __device__ __forceinline__ int mixed_lookup(const PlanView& v, int s, float hs, float* T,
                                             dust_counters* cnt) {
-    if (v.polish) {
+    if constexpr (MODE == MODE_MIXED_POLISH) {
         double lnT0;
         return table_lookup_f64(v, s, (double)hs, T, &lnT0, cnt);
+    } else {
+        return table_lookup_f32(v, s, hs, T, cnt);
     }
-    return table_lookup_f32(v, s, hs, T, cnt);
 }
 
-// Exact FP64 solve of one pending pair (status 1, 2 or 3 from
-// table_lookup_f64) by the whole wave: every lane calls it with the same
-// arguments and receives T.  Counts the pair as out of table.
+// Bracket [*lo, *hi] and start *lnT0 (ln T) of the exact solve of a pair
+// the table lookup did not take, y = ln H': below the table (T < T_0), above
+// it, a grain whose table is not finite, or a pair on the table's edge that
+// FP32 rounding put outside.  Starts extrapolate the end interval's slope.
+__device__ inline void pending_bracket(const PlanView& v, int s, double y, double* lo,
+                                       double* hi, double* lnT0) {
+    const double ylo = v.ylo[s], yhi = v.yhi[s];
+    const int N = v.N;
+    const double lnTmax = v.lnTmin + (N - 1) * v.hstep;
+    const double* f = v.fwd + (int64_t)s * N;
+    *lo = -6.907755278982137;  // ln 1e-3
+    *hi = 16.11809565095832;   // ln 1e7
+    if (!(__builtin_isfinite(ylo) && __builtin_isfinite(yhi) && yhi > ylo)) {
+        *lnT0 = 0.5 * (*lo + *hi);
+    } else if (y < ylo) {
+        *hi = v.lnTmin;
+        *lnT0 = v.lnTmin + (y - ylo) * v.hstep / (f[1] - f[0]);
+    } else if (y > yhi) {
+        *lo = lnTmax;
+        *lnT0 = lnTmax + (y - yhi) * v.hstep / (f[N - 1] - f[N - 2]);
+    } else {
+        *lnT0 = v.lnTmin + (y - ylo) / (yhi - ylo) * (lnTmax - v.lnTmin);
+    }
+}
+
+// Exact FP64 solve of one pair the table lookup did not take, by the whole
+// wave: every lane calls it with the same arguments and receives T.  Counts
+// the pair as out of table.
 __device__ inline float wave_solve_pending(const PlanView& v, int s, double hs,
                                            dust_counters* cnt) {
-    float T;
-    double lnT0 = 0.0;
-    const int st = table_lookup_f64(v, s, hs, &T, &lnT0, nullptr);
-    if (st == 0) return T;  // cannot happen for a pending pair; harmless
-    const double lnTmax = v.lnTmin + (v.N - 1) * v.hstep;
-    const double lo = (st == 2) ? lnTmax : -6.907755278982137;  // ln 1e-3
-    const double hi = (st == 1) ? v.lnTmin : 16.11809565095832;  // ln 1e7
+    double lo, hi, lnT0;
+    pending_bracket(v, s, ln_f32_value(hs, v.lntab), &lo, &hi, &lnT0);
     bool ok = false;
     const double lnT = wave_solve_exact_f64(v, s, hs, lo, hi, lnT0, &ok);
     if (cnt && (threadIdx.x & 63) == 0) {
         count(&cnt->n_out_of_table);
         if (!ok) count(&cnt->n_unconverged);
     }
-    return (float)exp(lnT);
+    return (float)exp_f64(lnT);
 }
 
 // ---------------------------------------------------------------------------

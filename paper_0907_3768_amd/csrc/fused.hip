@@ -7,8 +7,12 @@
 namespace dust {
 namespace {
 
+// Five resident waves per SIMD: the register budget this asks of the
+// compiler (96) keeps the phases of different tiles overlapping; six made
+// the large-grid instances spill.
 template <int MODE, int NTW>
-__global__ __launch_bounds__(256) void fused_kernel(PlanView v, int64_t C,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void fused_kernel(
+    PlanView v, int64_t C,
                                                    const float* __restrict__ J, int64_t ldj,
                                                    const float* __restrict__ m,
                                                    float* __restrict__ T, int64_t ldt,
@@ -40,9 +44,13 @@ hipError_t launch_as_ntw(const PlanView& v, int64_t C, const float* J, int64_t l
                          int64_t ldt, dust_counters* cnt, hipStream_t st) {
     const size_t lds = sizeof(float) * FUSED_TC * v.Sp + STAGE_BYTES + SOLVE_LDS_BYTES;
     const dim3 grid((unsigned)((C + FUSED_TC - 1) / FUSED_TC));
-    if (v.mode == DUST_MIXED)
+    const int km = kernel_mode(v);
+    if (km == DUST_MIXED)
         hipLaunchKernelGGL((absorb_solve_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v,
                            C, J, ldj, T, ldt, cnt);
+    else if (km == MODE_MIXED_POLISH)
+        hipLaunchKernelGGL((absorb_solve_kernel<MODE_MIXED_POLISH, NTW>), grid, dim3(256), lds,
+                           st, v, C, J, ldj, T, ldt, cnt);
     else if (v.mode == DUST_TABLE_LINEAR)
         hipLaunchKernelGGL((absorb_solve_kernel<DUST_TABLE_LINEAR, NTW>), grid, dim3(256), lds,
                            st, v, C, J, ldj, T, ldt, cnt);
@@ -58,9 +66,13 @@ hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj,
                       hipStream_t st) {
     const size_t lds = fused_lds_bytes(FUSED_TC, v.Sp);
     const dim3 grid((unsigned)((C + FUSED_TC - 1) / FUSED_TC));
-    if (v.mode == DUST_MIXED)
+    const int km = kernel_mode(v);
+    if (km == DUST_MIXED)
         hipLaunchKernelGGL((fused_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v, C, J, ldj,
                            m, T, ldt, L, ldl, cnt);
+    else if (km == MODE_MIXED_POLISH)
+        hipLaunchKernelGGL((fused_kernel<MODE_MIXED_POLISH, NTW>), grid, dim3(256), lds, st, v, C,
+                           J, ldj, m, T, ldt, L, ldl, cnt);
     else if (v.mode == DUST_TABLE_LINEAR)
         hipLaunchKernelGGL((fused_kernel<DUST_TABLE_LINEAR, NTW>), grid, dim3(256), lds, st, v, C,
                            J, ldj, m, T, ldt, L, ldl, cnt);

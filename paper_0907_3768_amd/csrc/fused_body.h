@@ -84,6 +84,7 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
         }
     };
 
+    const int nsteps = v.NLp / 32;  // k-steps (NLp is a multiple of 32)
     // Weight fragments of one k-step for the wave's tiles (bf16 hi/lo, or
     // 8 FP32 values).
     struct KFrag {
@@ -95,19 +96,21 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
         for (int t = 0; t < NTW; ++t) {
             const int tile = tg + wave + 4 * t;
             if (tile < tiles) {
-                const int64_t o = (int64_t)(tile * 16 + row) * v.NLp + k0 + kq * 8;
+                // fragment order: this lane's 8 values of (tile, k-step) (see kfrag_bf16)
+                const int64_t fr = (int64_t)tile * nsteps + (k0 >> 5);
                 if constexpr (BF) {
+                    const int64_t o = (fr * 64 + lane) * 8;
                     f.hi[t] = *reinterpret_cast<const bf16x8*>(v.khi + o);
                     f.lo[t] = *reinterpret_cast<const bf16x8*>(v.klo + o);
                 } else {
+                    const int64_t o = (fr * 128 + lane) * 4;
                     f.f0[t] = *reinterpret_cast<const float4*>(v.kf + o);
-                    f.f1[t] = *reinterpret_cast<const float4*>(v.kf + o + 4);
+                    f.f1[t] = *reinterpret_cast<const float4*>(v.kf + o + 256);
                 }
             }
         }
     };
 
-    const int nsteps = v.NLp / 32;                    // k-steps (NLp is a multiple of 32)
     const int nchunks = (nsteps + ABS_KSTEPS - 1) / ABS_KSTEPS;
     // Grain tiles in groups of 4 NTW (one pass over J each).
     for (int tg = 0; tg < tiles; tg += 4 * NTW) {
@@ -195,7 +198,7 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
     const int n = TC * v.Sp;
     int* sCount = sSolve;
     int* sList = sSolve + 4;
-    if constexpr (MODE == DUST_MIXED) {
+    if constexpr (mixed_mode(MODE)) {
         if (threadIdx.x == 0) *sCount = 0;
         __syncthreads();
     }
@@ -219,8 +222,8 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
             float h = sH[i];
             if (v.q) h += v.q[c * v.ldq + s] * v.hscale[s];
             float t;
-            if constexpr (MODE == DUST_MIXED) {
-                if (mixed_lookup(v, s, h, &t, cnt) != 0) {
+            if constexpr (mixed_mode(MODE)) {
+                if (mixed_lookup<MODE>(v, s, h, &t, cnt) != 0) {
                     const int k = atomicAdd(sCount, 1);
                     if (k < PENDING_CAP) sList[k] = i;
                     sH[i] = -h;  // pending: solved below
@@ -243,7 +246,7 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
     if constexpr (MODE == DUST_PLAIN_FP32) {
         if (cnt) wave_count_add(&cnt->n_newton_evals, evals);
     }
-    if constexpr (MODE == DUST_MIXED) {
+    if constexpr (mixed_mode(MODE)) {
         __syncthreads();
         for (;;) {
             const int total = *sCount;
@@ -288,12 +291,6 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
     uint32_t* sChunk = reinterpret_cast<uint32_t*>(sH + n);
     fill_chunk_min<TC>(sH, sChunk, v.Sp);
     __syncthreads();
-    float mc[TC];
-#pragma unroll
-    for (int cc = 0; cc < TC; ++cc) {
-        const int64_t c = c0 + cc;
-        mc[cc] = (c < C) ? ((m ? m[c] : 1.0f) * v.escale) : 0.0f;
-    }
     for (int l0 = 0; l0 < v.NL; l0 += blockDim.x) {
         const int l = l0 + threadIdx.x;
         const bool lv = l < v.NL;
@@ -304,7 +301,8 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
         if (lv) {
 #pragma unroll
             for (int cc = 0; cc < TC; ++cc)
-                if (c0 + cc < C) L[(c0 + cc) * ldl + l] = acc[cc] * mc[cc];
+                if (c0 + cc < C)
+                    L[(c0 + cc) * ldl + l] = acc[cc] * ((m ? m[c0 + cc] : 1.0f) * v.escale);
         }
     }
 }

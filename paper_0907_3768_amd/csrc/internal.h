@@ -40,9 +40,9 @@ struct PlanView {
     const float* hinv;     // 2^-es
     const float* gs;       // Eq. 11 offset: log10 of 4 pi 2^-es, plus the size terms
     // [Sp][NLp] tables
-    const float* kf;       // K' = C dlam 2^es (FP32)
-    const __bf16* khi;     // bf16(K')
-    const __bf16* klo;     // bf16(K' - khi)
+    const float* kf;       // K' = C dlam 2^es (FP32), fragment order (kfrag_f32)
+    const __bf16* khi;     // bf16(K'), fragment order (kfrag_bf16)
+    const __bf16* klo;     // bf16(K' - khi), fragment order
     const float* kb;       // K' c1 lam^-5 (FP32): the solve's Planck weights
     const float* em;       // w C c1 lam^-5 2^-ge (FP32): the emission weights
     float escale;          // 2^ge
@@ -77,6 +77,21 @@ struct PlanView {
     int64_t ldq;
     int warm;              // plain: start Newton from the T already in the output
 };
+
+// Positions of K'[s][l] (s < Sp, l < NLp) in the fragment-ordered weight
+// tables.  Grain tile t = s / 16, k-step j = l / 32; the 64 lanes of a wave
+// (lane = 16 q + row) hold row s = 16 t + row and wavelengths
+// 32 j + 8 q .. 32 j + 8 q + 7.  bf16: 8 values per lane, one fragment of
+// 64 x 8 values per (t, j).  FP32: the same 8 values as two halves of 4, each
+// half a contiguous 64 x 4 block.
+__host__ __device__ inline int64_t kfrag_bf16(const PlanView& v, int s, int l) {
+    const int t = s >> 4, row = s & 15, j = l >> 5, q = (l >> 3) & 3, e = l & 7;
+    return (((int64_t)t * (v.NLp >> 5) + j) * 64 + (q * 16 + row)) * 8 + e;
+}
+__host__ __device__ inline int64_t kfrag_f32(const PlanView& v, int s, int l) {
+    const int t = s >> 4, row = s & 15, j = l >> 5, q = (l >> 3) & 3, e = l & 7;
+    return ((((int64_t)t * (v.NLp >> 5) + j) * 2 + (e >> 2)) * 64 + (q * 16 + row)) * 4 + (e & 3);
+}
 
 }  // namespace dust
 
@@ -114,8 +129,18 @@ hipError_t launch_absorb(const PlanView& v, int64_t C, const float* J, int64_t l
                          float* H, int64_t ldh, hipStream_t st);
 hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ldh,
                         float* T, int64_t ldt, dust_counters* cnt, hipStream_t st);
-// Modes whose heating runs on bf16 hi+lo MFMA and whose T comes from a table.
+// Kernel forms: the public modes, plus the mixed mode with its FP64 polish
+// (a separate instantiation, so that the default form carries none of the
+// polish's FP64 code and registers).
+constexpr int MODE_MIXED_POLISH = 3;
+// Forms whose heating runs on bf16 hi+lo MFMA and whose T comes from a table.
 __host__ __device__ constexpr bool table_mode(int mode) { return mode != DUST_PLAIN_FP32; }
+__host__ __device__ constexpr bool mixed_mode(int mode) {
+    return mode == DUST_MIXED || mode == MODE_MIXED_POLISH;
+}
+inline int kernel_mode(const PlanView& v) {
+    return (v.mode == DUST_MIXED && v.polish) ? MODE_MIXED_POLISH : v.mode;
+}
 hipError_t launch_emit(const PlanView& v, int64_t C, const float* T, int64_t ldt,
                        const float* m, float* L, int64_t ldl, hipStream_t st);
 hipError_t launch_absorb_solve(const PlanView& v, int64_t C, const float* J, int64_t ldj,

@@ -2,7 +2,7 @@
 //
 //  prep  (the paper's first kernel, Section 4.1): K = C dlam per grain and
 //        wavelength, scaled per grain by an exact power of two, in FP32 and as
-//        a bf16 hi+lo pair; the solve weights K' c1 lam^-5; the emission
+//        a bf16 hi+lo pair (both in MFMA fragment order); the solve weights K' c1 lam^-5; the emission
 //        weights w C c1 lam^-5 (Eq. 10 without the mass); the wavelength
 //        exponent table nu = -c2 log2(e) / lam.
 //  ltab  (mixed mode): per grain, y_k = ln P'(T_k) at log-spaced T_k, in
@@ -34,6 +34,9 @@ __global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __r
     const int s = blockIdx.y;
     if (l >= v.NLp) return;
     const int64_t o = (int64_t)s * v.NLp + l;
+    // The heating weights are stored in MFMA fragment order, so that one
+    // wave's fragment of one grain tile and k-step is a contiguous 1 KB.
+    const int64_t ob = kfrag_bf16(v, s, l), of = kfrag_f32(v, s, l);
     if (s == 0) {
         nu[l] = (l < v.NL) ? (float)(-RAD_C2 * LOG2E / lam[l]) : -1.0f;
         if (l < v.NL) c2l[l] = RAD_C2 / lam[l];
@@ -46,16 +49,16 @@ __global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __r
         const float kff = (float)K;
         const __bf16 hi = (__bf16)kff;
         const __bf16 lo = (__bf16)(float)(K - (double)(float)hi);
-        kf[o] = kff;
-        khi[o] = hi;
-        klo[o] = lo;
+        kf[of] = kff;
+        khi[ob] = hi;
+        klo[ob] = lo;
         kb[o] = (float)(K * c1l5);
         em[o] = (float)ldexp(w[s] * C * c1l5, -ge);
         kdb[(int64_t)s * v.NL + l] = K * c1l5;
     } else {
-        kf[o] = 0.0f;
-        khi[o] = (__bf16)0.0f;
-        klo[o] = (__bf16)0.0f;
+        kf[of] = 0.0f;
+        khi[ob] = (__bf16)0.0f;
+        klo[ob] = (__bf16)0.0f;
         kb[o] = 0.0f;
         em[o] = 0.0f;
     }

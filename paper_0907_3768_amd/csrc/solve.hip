@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) void solve_table_kernel(PlanView v, int64_t C,
 // One thread per (cell, grain) in row-major order: coalesced H and T.  Pairs
 // outside the table go to an LDS list and are then solved exactly by the
 // block's waves in turn (one pair per wave at a time, lanes over wavelength).
+template <int MODE>
 __global__ __launch_bounds__(256) void solve_mixed_kernel(PlanView v, int64_t C,
                                                           const float* __restrict__ H,
                                                           int64_t ldh, float* __restrict__ T,
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256) void solve_mixed_kernel(PlanView v, int64_t C,
     const float hs = h * v.hscale[s];
     float t = 0.0f;
     if (active) {
-        if (mixed_lookup(v, s, hs, &t, cnt) != 0)
+        if (mixed_lookup<MODE>(v, s, hs, &t, cnt) != 0)
             sList[atomicAdd(&sCount, 1)] = threadIdx.x;
         else
             T[c * ldt + s] = t;
@@ -136,8 +137,13 @@ hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ld
     if (C == 0) return hipSuccess;
     if (v.mode == DUST_MIXED) {
         const int64_t n = C * v.S;
-        hipLaunchKernelGGL(solve_mixed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           st, v, C, H, ldh, T, ldt, cnt);
+        if (v.polish)
+            hipLaunchKernelGGL(solve_mixed_kernel<MODE_MIXED_POLISH>,
+                               dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, C, H, ldh,
+                               T, ldt, cnt);
+        else
+            hipLaunchKernelGGL(solve_mixed_kernel<DUST_MIXED>, dim3((unsigned)((n + 255) / 256)),
+                               dim3(256), 0, st, v, C, H, ldh, T, ldt, cnt);
     } else if (v.mode == DUST_TABLE_LINEAR) {
         const int64_t n = C * v.S;
         hipLaunchKernelGGL(solve_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
