@@ -101,7 +101,7 @@ void free_plan(dust_plan* p) {
                     p->d_hscale, p->d_hinv, p->d_gs, p->d_kf,  p->d_kb,   p->d_em,   p->d_khi,
                     p->d_klo, p->d_kdb,  p->d_c2l,  p->d_fwd, p->d_inv, p->d_ylo,  p->d_yhi,
                     p->d_dyinv, p->d_texp, p->d_lntab, p->d_F, p->d_kidx, p->d_invf,
-                    p->d_ylof, p->d_dyinvf};
+                    p->d_ylof, p->d_dyinvf, p->d_ku};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -142,7 +142,9 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
             const double lm = g->lambda[l];
             const double K = g->c_abs[(int64_t)s * NL + l] * g->dlambda[l];
             kmax = fmax(kmax, K);
-            kbmax = fmax(kbmax, K * RAD_C1 / (lm * lm * lm * lm * lm));
+            // the solve's weights and its slope weights (times c2 log2(e) / lam)
+            kbmax = fmax(kbmax, K * RAD_C1 / (lm * lm * lm * lm * lm) *
+                                    fmax(1.0, RAD_C2 * LOG2E / lm));
             emax = fmax(emax, g->weight[s] * g->c_abs[(int64_t)s * NL + l] * RAD_C1 /
                                   (lm * lm * lm * lm * lm));
         }
@@ -151,7 +153,7 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
         es[s] = -e;
         if (kmax > 0.0 && !(ldexp(kbmax, -e) < 1e37))
             return set_error(DUST_EUNSUPPORTED,
-                             "C dlam c1 lam^-5 spans more than FP32 holds for a grain");
+                             "C dlam c1 lam^-5 (c2 / lam) spans more than FP32 holds for a grain");
         if (es[s] < -126 || es[s] > 126)
             return set_error(DUST_EUNSUPPORTED, "C dlam outside the FP32 exponent range");
         hscale[s] = ldexpf(1.0f, es[s]);
@@ -210,6 +212,7 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     ALLOC(p->d_gs, Sp);
     ALLOC(p->d_kf, (size_t)Sp * NLp);
     ALLOC(p->d_kb, (size_t)Sp * NLp);
+    ALLOC(p->d_ku, (size_t)Sp * NLp);
     ALLOC(p->d_em, (size_t)Sp * NLp);
     ALLOC(p->d_khi, (size_t)Sp * NLp);
     ALLOC(p->d_klo, (size_t)Sp * NLp);
@@ -284,6 +287,7 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     v.khi = p->d_khi;
     v.klo = p->d_klo;
     v.kb = p->d_kb;
+    v.ku = p->d_ku;
     v.em = p->d_em;
     v.escale = ldexpf(1.0f, ge);
     v.kdb = p->d_kdb;

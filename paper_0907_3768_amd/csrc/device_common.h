@@ -147,6 +147,121 @@ __device__ __forceinline__ double rcp_f64(double x) {
 }
 
 // ---------------------------------------------------------------------------
+// Smallest value over the wave, the same in every lane (a scalar).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_min_f32(float x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fminf(x, __shfl_xor(x, off, 64));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// First wavelength index l with u_l < lim, where u_l = -nu[l] decreases with
+// l (NL if none); lim is wave-uniform, so the search runs on scalar loads.
+__device__ __forceinline__ int first_u_below(const float* __restrict__ nu, int NL, float lim) {
+    int a = 0, b = NL;
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (-nu[mid] < lim) b = mid; else a = mid + 1;
+    }
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// Plain FP32 solve of Eq. 7 for one grain and up to 64 cells, one cell per
+// lane: the iteration of solve_newton_f32 (Newton on ln P = ln H in ln T,
+// bracket safeguard, stop at |ln(P/H)| <= tol after applying the step),
+// with the grain's weights wave-uniform (scalar loads) and the sums of
+// Eq. 7 split by wavelength at every evaluation from the wave's hottest
+// active cell, t = u_l / T:
+//   t >= 150 for every lane: the term is exactly 0 in FP32, skipped;
+//   t >= 24 for every lane: 1/(2^t - 1) = 2^-t to FP32 rounding (one
+//                           exponential, no reciprocal);
+//   otherwise: the exact 1/(2^t - 1).
+// The slope uses ku = kb u: T dP/dT = ln 2 / T sum_l ku_l r (1 + r).
+// Every lane of the wave must call it (`live` false for a lane without a
+// pair).  *evals receives the lane's number of evaluations.
+// ---------------------------------------------------------------------------
+__device__ inline float solve_newton_wave(const float* __restrict__ kb,
+                                          const float* __restrict__ ku,
+                                          const float* __restrict__ nu, int NL, bool live,
+                                          float hs, float gs, float tol, int maxit, float tstart,
+                                          int* evals, dust_counters* cnt) {
+    int nev = 0;
+    float result = 0.0f;
+    bool active = false;
+    float lnH = 0.0f, lnT = 0.0f;
+    if (live) {
+        if (!(hs >= 0.0f) || __builtin_isinf(hs)) {
+            if (cnt) count(&cnt->n_nonfinite);
+            result = __builtin_nanf("");
+        } else if (hs > 0.0f) {
+            active = true;
+            lnH = logf(hs);
+            lnT = (tstart > 0.0f && tstart < INFINITY) ? logf(tstart) : guess_lnT(hs, gs);
+        }
+    }
+    const bool solving = active;
+    float lo = -INFINITY, hi = INFINITY;
+    bool done = false;
+    for (int it = 0; it < maxit; ++it) {
+        if (__ballot(active) == 0) break;
+        const float invT = active ? expf(-lnT) : INFINITY;
+        // hottest active cell; the split only chooses between forms that are
+        // exact to FP32 rounding there, so an approximate reciprocal will do
+        const float tinv = __builtin_amdgcn_rcpf(wave_min_f32(invT));
+        const int l1 = first_u_below(nu, NL, 150.0f * tinv);
+        const int l2 = first_u_below(nu, NL, 24.0f * tinv);
+        float p = 0.0f, d = 0.0f;
+#pragma unroll 4
+        for (int l = l1; l < l2; ++l) {
+            const float y = __builtin_amdgcn_exp2f(nu[l] * invT);
+            p = fmaf(kb[l], y, p);
+            d = fmaf(ku[l], y, d);
+        }
+#pragma unroll 4
+        for (int l = l2; l < NL; ++l) {
+            const float r = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu[l] * invT)) - 1.0f);
+            p = fmaf(kb[l], r, p);
+            d = fmaf(ku[l], fmaf(r, r, r), d);
+        }
+        if (active) {
+            ++nev;
+            // A start far from the root (a warm start can be anywhere) may
+            // leave the sum unusable; step towards the Eq. 11 guess, or bisect
+            // once the other end of the bracket is known.
+            if (!(p < INFINITY)) {
+                hi = lnT;
+                lnT = (lo > -INFINITY) ? 0.5f * (lo + hi) : fminf(lnT - 1.0f, guess_lnT(hs, gs));
+            } else if (!(p > 0.0f)) {
+                lo = lnT;
+                lnT = (hi < INFINITY) ? 0.5f * (lo + hi) : fmaxf(lnT + 1.0f, guess_lnT(hs, gs));
+            } else {
+                const float r = logf(p) - lnH;                 // ln(P / H)
+                const float slope = 0.69314718f * invT * d / p;  // d ln P / d ln T
+                if (r < 0.0f) lo = lnT; else hi = lnT;
+                float next = lnT - r / slope;
+                if (fabsf(r) <= tol) {
+                    lnT = next;
+                    done = true;
+                    active = false;
+                } else {
+                    if (!(next > lo && next < hi))
+                        next = (lo > -INFINITY && hi < INFINITY) ? 0.5f * (lo + hi)
+                                                                 : lnT - copysignf(1.0f, r);
+                    lnT = next;
+                }
+            }
+        }
+    }
+    *evals = nev;
+    if (solving) {
+        if (!done && cnt) count(&cnt->n_unconverged);
+        result = expf(lnT);
+    }
+    return result;
+}
+
+// ---------------------------------------------------------------------------
 // e^x in FP64 with few registers: Cody-Waite reduction x = k ln 2 + r
 // (|r| <= ln(2)/2, ln 2 in two parts so that k ln2_hi is exact), e^r from its
 // Taylor series to r^12 (truncation < 2e-16 relative), then 2^k.  Overflow

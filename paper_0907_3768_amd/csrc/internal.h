@@ -44,6 +44,7 @@ struct PlanView {
     const __bf16* khi;     // bf16(K'), fragment order (kfrag_bf16)
     const __bf16* klo;     // bf16(K' - khi), fragment order
     const float* kb;       // K' c1 lam^-5 (FP32): the solve's Planck weights
+    const float* ku;       // kb * c2 log2(e) / lam: weights of the solve's slope
     const float* em;       // w C c1 lam^-5 2^-ge (FP32): the emission weights
     float escale;          // 2^ge
     // float64 tables of the mixed solve
@@ -106,7 +107,7 @@ struct dust_plan {
     double *d_lam, *d_dlam, *d_cabs, *d_w, *d_size;
     int* d_es;
     // derived device tables
-    float *d_nu, *d_hscale, *d_hinv, *d_gs, *d_kf, *d_kb, *d_em;
+    float *d_nu, *d_hscale, *d_hinv, *d_gs, *d_kf, *d_kb, *d_ku, *d_em;
     __bf16 *d_khi, *d_klo;
     double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv, *d_fwd, *d_texp;
     double* d_F;  // [N][NL] Planck factors of the table temperatures

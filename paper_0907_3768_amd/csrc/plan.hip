@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __r
                                                    const double* __restrict__ w,
                                                    const int* __restrict__ es, int ge,
                                                    float* nu, float* kf, __bf16* khi,
-                                                   __bf16* klo, float* kb, float* em,
+                                                   __bf16* klo, float* kb, float* ku, float* em,
                                                    double* kdb, double* c2l) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
@@ -53,6 +53,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __r
         khi[ob] = hi;
         klo[ob] = lo;
         kb[o] = (float)(K * c1l5);
+        ku[o] = (float)(K * c1l5 * (RAD_C2 * LOG2E / lm));
         em[o] = (float)ldexp(w[s] * C * c1l5, -ge);
         kdb[(int64_t)s * v.NL + l] = K * c1l5;
     } else {
@@ -60,6 +61,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __r
         khi[ob] = (__bf16)0.0f;
         klo[ob] = (__bf16)0.0f;
         kb[o] = 0.0f;
+        ku[o] = 0.0f;
         em[o] = 0.0f;
     }
 }
@@ -183,7 +185,7 @@ hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
     const PlanView& v = p->view;
     dim3 g1((v.NLp + 255) / 256, v.Sp);
     hipLaunchKernelGGL(prep_kernel, g1, dim3(256), 0, st, v, p->d_lam, p->d_dlam, p->d_cabs,
-                       p->d_w, p->d_es, p->ge, p->d_nu, p->d_kf, p->d_khi, p->d_klo, p->d_kb,
+                       p->d_w, p->d_es, p->ge, p->d_nu, p->d_kf, p->d_khi, p->d_klo, p->d_kb, p->d_ku,
                        p->d_em, p->d_kdb, p->d_c2l);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !table_mode(v.mode)) return e;

@@ -45,19 +45,19 @@ __global__ __launch_bounds__(256) void solve_plain_kernel(PlanView v, int64_t C,
         sX[cc * ST + sl] = h * v.hscale[g0 + sl];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool live = lane < rows;
     int evals = 0;
     for (int sl = wave; sl < G; sl += 4) {
-        const int s = g0 + sl;
-        if (live) {
-            const float t0 = v.warm ? T[(c0 + lane) * ldt + s] : 0.0f;
-            int ev;
-            sX[lane * ST + sl] = solve_newton_f32(v.kb + (int64_t)s * v.NLp, v.nu, v.NL,
-                                                  sX[lane * ST + sl], v.gs[s], v.tol, v.maxit,
-                                                  t0, &ev, cnt);
-            evals += ev;
-        }
+        const int s = g0 + sl;  // wave-uniform: the grain's weights come as scalars
+        const float t0 = (live && v.warm) ? T[(c0 + lane) * ldt + s] : 0.0f;
+        int ev;
+        const float t = solve_newton_wave(v.kb + (int64_t)s * v.NLp, v.ku + (int64_t)s * v.NLp,
+                                          v.nu, v.NL, live, live ? sX[lane * ST + sl] : 0.0f,
+                                          v.gs[s], v.tol, v.maxit, t0, &ev, cnt);
+        if (live) sX[lane * ST + sl] = t;
+        evals += ev;
     }
     if (cnt) {
 #pragma unroll
