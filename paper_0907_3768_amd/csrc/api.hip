@@ -79,7 +79,7 @@ dust_status resolve_options(const dust_options* in, dust_options* o) {
     if (d.fused_kernels < 0 || d.fused_kernels > 2)
         return set_error(DUST_EINVAL, "fused_kernels must be 0, 1 or 2");
     if (d.reserved != 0) return set_error(DUST_EINVAL, "dust_options.reserved must be 0");
-    d.polish = d.polish != 0;
+    d.f32_lookup = d.f32_lookup != 0;
     if (d.ltab_tmin == 0.0) d.ltab_tmin = lin ? 3.0 : 2.7;
     if (d.ltab_tmax == 0.0) d.ltab_tmax = lin ? 1500.0 : 3000.0;
     if (!(d.ltab_tmin > 0.0) || !(d.ltab_tmax > d.ltab_tmin) || !isfinite(d.ltab_tmax) ||
@@ -99,7 +99,7 @@ void free_plan(dust_plan* p) {
     if (!p) return;
     void* ptrs[] = {p->d_lam, p->d_dlam, p->d_cabs, p->d_w,   p->d_size, p->d_es,   p->d_nu,
                     p->d_hscale, p->d_hinv, p->d_gs, p->d_kf,  p->d_kb,   p->d_em,   p->d_khi,
-                    p->d_klo, p->d_kdb,  p->d_c2l,  p->d_fwd, p->d_inv, p->d_ylo,  p->d_yhi,
+                    p->d_klo, p->d_kdb,  p->d_c2l,  p->d_fwd, p->d_ylo,  p->d_yhi,
                     p->d_dyinv, p->d_texp, p->d_lntab, p->d_F, p->d_kidx, p->d_invf,
                     p->d_ylof, p->d_dyinvf, p->d_ku};
     for (void* q : ptrs)
@@ -223,7 +223,6 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
         if (lin) {
             ALLOC(p->d_kidx, (size_t)S * p->M);
         } else {
-            ALLOC(p->d_inv, (size_t)S * p->M);
             ALLOC(p->d_invf, (size_t)S * (p->M - 1));
             ALLOC(p->d_ylof, S);
             ALLOC(p->d_dyinvf, S);
@@ -293,7 +292,6 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     v.kdb = p->d_kdb;
     v.c2l = p->d_c2l;
     v.fwd = p->d_fwd;
-    v.inv = p->d_inv;
     v.ylo = p->d_ylo;
     v.yhi = p->d_yhi;
     v.dyinv = p->d_dyinv;
@@ -308,7 +306,7 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     v.invf = p->d_invf;
     v.ylof = p->d_ylof;
     v.dyinvf = p->d_dyinvf;
-    v.polish = o.polish;
+    v.f32_lookup = o.f32_lookup;
     v.tstep = tstep;
     v.q = nullptr;
     v.ldq = 0;

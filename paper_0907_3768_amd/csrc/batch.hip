@@ -218,9 +218,9 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     for (int g = 0; g < n_grids; ++g) {
         const dust_plan* p = plans[g];
         if (!p) return set_error(DUST_EINVAL, "plans[" + std::to_string(g) + "] is NULL");
-        if (p->opt.mode != DUST_MIXED || p->opt.polish)
+        if (p->opt.mode != DUST_MIXED || p->opt.f32_lookup)
             return set_error(DUST_EUNSUPPORTED,
-                             "batched launches take DUST_MIXED plans without the FP64 polish");
+                             "batched launches take DUST_MIXED plans with the FP64 polish");
         if (n_cells[g] < 0 || n_cells[g] > ((int64_t)1 << 36))
             return set_error(DUST_EINVAL, "n_cells out of range");
         const int64_t c = n_cells[g];

@@ -379,76 +379,14 @@ __device__ __forceinline__ int stencil_start(int k, int N) {
     return j0 < 0 ? 0 : (j0 > N - 4 ? N - 4 : j0);
 }
 
-// ---------------------------------------------------------------------------
-// Cubic Hermite on [0, 1] (inverse table).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double hermite(double t, double y0, double m0, double y1, double m1) {
-    const double t2 = t * t, t3 = t2 * t;
-    return (2.0 * t3 - 3.0 * t2 + 1.0) * y0 + (t3 - 2.0 * t2 + t) * m0 +
-           (3.0 * t2 - 2.0 * t3) * y1 + (t3 - t2) * m1;
-}
 
 // ---------------------------------------------------------------------------
-// Mixed solve of Eq. 7 from the grain's FP64 tables.  y = ln H' is located in
-// the inverse table (ln T at uniform steps of y: no search), whose cubic
-// Hermite gives a starting ln T within about 1e-6; the forward table
-// y_k = ln P'(T_k) around it gives the cubic through four neighbouring
-// points, on which one FP64 Newton step polishes ln T (the start is within
-// about 1e-3 of a table step, so the step leaves an error near 1e-12 of one).
-// T = T_k e^d with T_k from a table and e^d, 0 <= d < hstep, from its series.
-// Returns 0 with *T set, or, for a pair the table does not cover, a pending
-// code with *lnT0 a starting point for the exact solve:
-//   1: below the table, 2: above it, 3: the grain's table is not finite.
-// ---------------------------------------------------------------------------
-__device__ inline int table_lookup_f64(const PlanView& v, int s, double hs, float* T,
-                                       double* lnT0, dust_counters* cnt) {
-    if (!(hs >= 0.0) || __builtin_isinf(hs)) {
-        if (cnt) count(&cnt->n_nonfinite);
-        *T = __builtin_nanf("");
-        return 0;
-    }
-    if (hs == 0.0) { *T = 0.0f; return 0; }
-    const double y = ln_f32_value(hs, v.lntab);
-    const double ylo = v.ylo[s], yhi = v.yhi[s];
-    const int N = v.N, M = v.M;
-    const double* f = v.fwd + (int64_t)s * N;
-    if (!(__builtin_isfinite(ylo) && __builtin_isfinite(yhi))) { *lnT0 = 0.0; return 3; }
-    if (y < ylo) {  // extrapolate with the slope of the first interval
-        *lnT0 = v.lnTmin + (y - ylo) * v.hstep / (f[1] - f[0]);
-        return 1;
-    }
-    if (y > yhi) {
-        *lnT0 = v.lnTmin + (N - 1) * v.hstep + (y - yhi) * v.hstep / (f[N - 1] - f[N - 2]);
-        return 2;
-    }
-    // inverse table: ln T(y) at uniform nodes, as a position in table steps
-    const double uj = (y - ylo) * v.dyinv[s];
-    int j = (int)uj;
-    j = j < 0 ? 0 : (j > M - 2 ? M - 2 : j);
-    const double2* g = v.inv + (int64_t)s * M + j;
-    const double2 g0 = g[0], g1 = g[1];
-    const double kt = (hermite(uj - j, g0.x, g0.y, g1.x, g1.y) - v.lnTmin) * v.inv_hstep;
-    int k = (int)kt;
-    k = k < 0 ? 0 : (k > N - 2 ? N - 2 : k);
-    const int j0 = stencil_start(k, N);
-    double dp;
-    const double p = cubic4(kt - j0, f[j0], f[j0 + 1], f[j0 + 2], f[j0 + 3], &dp);
-    const double pos = kt - (p - y) * rcp_f64(dp);  // position in table steps
-    int kk = (int)pos;
-    kk = kk < 0 ? 0 : (kk > N - 1 ? N - 1 : kk);
-    const double d = (pos - kk) * v.hstep;
-    const double ed = 1.0 + d * (1.0 + d * (0.5 + d * (1.0 / 6.0 + d * (1.0 / 24.0 + d * (1.0 / 120.0)))));
-    *T = (float)(v.texp[kk] * ed);
-    return 0;
-}
-
-// ---------------------------------------------------------------------------
-// Default mixed solve of Eq. 7: the grain's inverse table ln T(y), y = ln H',
+// FP32 mixed solve of Eq. 7: the grain's inverse table ln T(y), y = ln H',
 // as a cubic Hermite in FP32 between the two nodes around y (one 16-byte
 // entry holds both).  FP32 rounding of y (|y| up to about 50) and of the
 // table leaves a relative T error of about 2e-6; the Hermite itself is far
 // below that.  Returns 0 with *T set, or nonzero for a pair outside the
-// table (then solved exactly; table_lookup_f64 classifies it).
+// table (then solved exactly).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int table_lookup_f32(const PlanView& v, int s, float hs, float* T,
                                                 dust_counters* cnt) {
@@ -471,15 +409,49 @@ __device__ __forceinline__ int table_lookup_f32(const PlanView& v, int s, float 
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Mixed solve of Eq. 7 with the FP64 polish: the FP32 lookup above gives the
+// start (ln T within about 2e-6); the grain's forward table
+// y_k = ln P'(T_k) (FP64, log-spaced T_k) gives the cubic through the four
+// points around it, on which one FP64 Newton step in the table position
+// solves y(ln T) = ln H' (the start is within a small fraction of a table
+// step, so the step leaves an error near 1e-12 of one).  Returns as
+// table_lookup_f32.
+// ---------------------------------------------------------------------------
+__device__ inline int table_lookup_polish(const PlanView& v, int s, float hs, float* T,
+                                          dust_counters* cnt) {
+    float t32;
+    const int st = table_lookup_f32(v, s, hs, &t32, cnt);
+    if (st != 0 || !(t32 > 0.0f) || !(t32 < INFINITY)) {
+        *T = t32;
+        return st;
+    }
+    const int N = v.N;
+    const double* f = v.fwd + (int64_t)s * N;
+    const double y = ln_f32_value((double)hs, v.lntab);
+    const double kt = ((double)logf(t32) - v.lnTmin) * v.inv_hstep;  // position in table steps
+    int k = (int)kt;
+    k = k < 0 ? 0 : (k > N - 2 ? N - 2 : k);
+    const int j0 = stencil_start(k, N);
+    double dp;
+    const double p = cubic4(kt - j0, f[j0], f[j0 + 1], f[j0 + 2], f[j0 + 3], &dp);
+    const double pos = kt - (p - y) * rcp_f64(dp);
+    // T leaves in FP32: e^(ln T) from the FP32 head of ln T and its small
+    // tail, e^head (1 + tail), relative error about 1.5e-7
+    const double lnT = v.lnTmin + pos * v.hstep;
+    const float head = (float)lnT;
+    *T = expf(head) * (1.0f + (float)(lnT - (double)head));
+    return 0;
+}
+
 // The lookup of a mixed kernel form.
 template <int MODE>
 __device__ __forceinline__ int mixed_lookup(const PlanView& v, int s, float hs, float* T,
                                             dust_counters* cnt) {
-    if constexpr (MODE == MODE_MIXED_POLISH) {
-        double lnT0;
-        return table_lookup_f64(v, s, (double)hs, T, &lnT0, cnt);
-    } else {
+    if constexpr (MODE == MODE_MIXED_F32) {
         return table_lookup_f32(v, s, hs, T, cnt);
+    } else {
+        return table_lookup_polish(v, s, hs, T, cnt);
     }
 }
 

@@ -48,8 +48,8 @@ hipError_t launch_as_ntw(const PlanView& v, int64_t C, const float* J, int64_t l
     if (km == DUST_MIXED)
         hipLaunchKernelGGL((absorb_solve_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v,
                            C, J, ldj, T, ldt, cnt);
-    else if (km == MODE_MIXED_POLISH)
-        hipLaunchKernelGGL((absorb_solve_kernel<MODE_MIXED_POLISH, NTW>), grid, dim3(256), lds,
+    else if (km == MODE_MIXED_F32)
+        hipLaunchKernelGGL((absorb_solve_kernel<MODE_MIXED_F32, NTW>), grid, dim3(256), lds,
                            st, v, C, J, ldj, T, ldt, cnt);
     else if (v.mode == DUST_TABLE_LINEAR)
         hipLaunchKernelGGL((absorb_solve_kernel<DUST_TABLE_LINEAR, NTW>), grid, dim3(256), lds,
@@ -70,8 +70,8 @@ hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj,
     if (km == DUST_MIXED)
         hipLaunchKernelGGL((fused_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v, C, J, ldj,
                            m, T, ldt, L, ldl, cnt);
-    else if (km == MODE_MIXED_POLISH)
-        hipLaunchKernelGGL((fused_kernel<MODE_MIXED_POLISH, NTW>), grid, dim3(256), lds, st, v, C,
+    else if (km == MODE_MIXED_F32)
+        hipLaunchKernelGGL((fused_kernel<MODE_MIXED_F32, NTW>), grid, dim3(256), lds, st, v, C,
                            J, ldj, m, T, ldt, L, ldl, cnt);
     else if (v.mode == DUST_TABLE_LINEAR)
         hipLaunchKernelGGL((fused_kernel<DUST_TABLE_LINEAR, NTW>), grid, dim3(256), lds, st, v, C,

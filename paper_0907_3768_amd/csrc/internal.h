@@ -51,16 +51,16 @@ struct PlanView {
     const double* kdb;     // [S][NL] K' c1 lam^-5 (FP64): exact power weights
     const double* c2l;     // [NL] c2 / lam (FP64)
     const double* fwd;     // [S][N] y_k = ln P'(T_k), T_k = exp(lnTmin + k hstep)
-    const double2* inv;    // [S][M] (ln T, dy * d ln T/dy) at uniform steps of y
     const double* ylo;     // [S] y_0
     const double* yhi;     // [S] y_{N-1}
     const double* dyinv;   // [S] (M - 1) / (yhi - ylo)
-    // FP32 copy of the inverse table for the default mixed lookup: per
-    // interval j, (ln T_j, m_j, ln T_{j+1}, m_{j+1}) in one 16-byte entry
+    // inverse table ln T(y) at M uniform steps of y (computed in FP64, stored
+    // in FP32): per interval j, (ln T_j, m_j, ln T_{j+1}, m_{j+1}) in one
+    // 16-byte entry, m = dy d ln T / dy
     const float4* invf;    // [S][M-1]
     const float* ylof;     // [S] float(ylo)
     const float* dyinvf;   // [S] float(dyinv)
-    int polish;            // mixed: FP64 table polish instead of the FP32 lookup
+    int f32_lookup;        // mixed: FP32 inverse-table lookup instead of the FP64 polish
     int N, M;
     double lnTmin, hstep;  // ln T_k = lnTmin + k hstep
     double inv_hstep;
@@ -111,7 +111,7 @@ struct dust_plan {
     __bf16 *d_khi, *d_klo;
     double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv, *d_fwd, *d_texp;
     double* d_F;  // [N][NL] Planck factors of the table temperatures
-    double2 *d_inv, *d_lntab;
+    double2* d_lntab;
     float4* d_invf;
     float *d_ylof, *d_dyinvf;
     int* d_kidx;  // table-linear search brackets [S][M]
@@ -130,17 +130,18 @@ hipError_t launch_absorb(const PlanView& v, int64_t C, const float* J, int64_t l
                          float* H, int64_t ldh, hipStream_t st);
 hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ldh,
                         float* T, int64_t ldt, dust_counters* cnt, hipStream_t st);
-// Kernel forms: the public modes, plus the mixed mode with its FP64 polish
-// (a separate instantiation, so that the default form carries none of the
-// polish's FP64 code and registers).
-constexpr int MODE_MIXED_POLISH = 3;
+// Kernel forms: the public modes, plus the mixed mode with the FP32
+// inverse-table lookup in place of the FP64 polish (a separate
+// instantiation, so that it carries none of the polish's FP64 code and
+// registers).
+constexpr int MODE_MIXED_F32 = 3;
 // Forms whose heating runs on bf16 hi+lo MFMA and whose T comes from a table.
 __host__ __device__ constexpr bool table_mode(int mode) { return mode != DUST_PLAIN_FP32; }
 __host__ __device__ constexpr bool mixed_mode(int mode) {
-    return mode == DUST_MIXED || mode == MODE_MIXED_POLISH;
+    return mode == DUST_MIXED || mode == MODE_MIXED_F32;
 }
 inline int kernel_mode(const PlanView& v) {
-    return (v.mode == DUST_MIXED && v.polish) ? MODE_MIXED_POLISH : v.mode;
+    return (v.mode == DUST_MIXED && v.f32_lookup) ? MODE_MIXED_F32 : v.mode;
 }
 hipError_t launch_emit(const PlanView& v, int64_t C, const float* T, int64_t ldt,
                        const float* m, float* L, int64_t ldl, hipStream_t st);

@@ -10,9 +10,9 @@
 //        the plan's scaled units -- as an FP64 matrix product of the grains'
 //        Planck weights with the Planck factors of the table temperatures.
 //  inv   (mixed mode): the inverse function ln T(y) and its derivative at
-//        uniform steps of y, from Newton on the forward table's piecewise
-//        cubic: in FP64 (the start of the optional FP64 polish) and in FP32
-//        pairs of nodes (the default lookup, one 16-byte load per pair).
+//        uniform steps of y, from Newton in FP64 on the forward table's
+//        piecewise cubic, stored as FP32 pairs of nodes (one 16-byte load
+//        per lookup).
 //  table-linear mode: the same matrix product gives P'(T_k) itself at evenly
 //        spaced T_k (the production table of Sections 2 and 5); kidx gives,
 //        at uniform steps of ln P', the last table point below, so that a
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void kidx_kernel(PlanView v, const double* __r
 // One thread per (grain, inverse node): ln T at y_j = ylo + j dy, by Newton
 // on the forward table's cubic, and dy * d ln T / dy there.
 __global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double* __restrict__ fwd,
-                                                  double2* inv, double* ylo, double* yhi,
+                                                  double* ylo, double* yhi,
                                                   double* dyinv, float2* invf, float* ylof,
                                                   float* dyinvf) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,7 +171,6 @@ __global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double* __re
     // d lnT / dy = hstep / (dy/dx), scaled by the node spacing dy = 1/dinv
     const double lnTj = v.lnTmin + ((double)j0 + x) * v.hstep;
     const double mj = v.hstep / dp / dinv;
-    inv[(int64_t)s * v.M + j] = make_double2(lnTj, mj);
     // the FP32 entries of the two intervals this node bounds
     const float2 nf = make_float2((float)lnTj, (float)mj);
     float2* row = invf + (int64_t)s * (v.M - 1) * 2;
@@ -203,7 +202,7 @@ hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
                            p->d_kidx, p->d_ylo, p->d_yhi, p->d_dyinv);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(inv_kernel, g3, dim3(256), 0, st, v, (const double*)p->d_fwd, p->d_inv,
+    hipLaunchKernelGGL(inv_kernel, g3, dim3(256), 0, st, v, (const double*)p->d_fwd,
                        p->d_ylo, p->d_yhi, p->d_dyinv, reinterpret_cast<float2*>(p->d_invf),
                        p->d_ylof, p->d_dyinvf);
     return hipGetLastError();

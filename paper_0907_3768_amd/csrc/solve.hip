@@ -9,8 +9,8 @@
 // leaves with coalesced stores; the Newton evaluations of the block are
 // counted with one atomic.
 // Mixed: one thread per (cell, grain) in row-major order (coalesced H and T),
-// an O(1) lookup in the grain's inverse table (FP32 Hermite, or optionally
-// the FP64 forward table with an FP64 Newton polish).
+// an O(1) lookup in the grain's tables (the inverse gives the start, an FP64
+// Newton step on the forward table polishes it; or the inverse alone in FP32).
 // Table-linear: the same layout, a bracketed search in the grain's table of
 // powers at evenly spaced T and linear interpolation (Sections 2 and 5).
 // Every form adds the optional extra heating Q to H first.
@@ -137,8 +137,8 @@ hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ld
     if (C == 0) return hipSuccess;
     if (v.mode == DUST_MIXED) {
         const int64_t n = C * v.S;
-        if (v.polish)
-            hipLaunchKernelGGL(solve_mixed_kernel<MODE_MIXED_POLISH>,
+        if (v.f32_lookup)
+            hipLaunchKernelGGL(solve_mixed_kernel<MODE_MIXED_F32>,
                                dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, C, H, ldh,
                                T, ldt, cnt);
         else

@@ -63,16 +63,16 @@ def _run(plan, J, m, path, counters=None):
 
 # --------------------------------------------------------------------------- small, full compare
 
-@pytest.mark.parametrize("mode", ["plain", "mixed", "mixed-polish"])
+@pytest.mark.parametrize("mode", ["plain", "mixed", "mixed-f32"])
 @pytest.mark.parametrize("path", ["separate", "fused", "fused2"])
 def test_small_full_compare(dev, mode, path):
     w = synth.WORKLOADS["small-1024x120x20"]
     g = w.grid()
     say(f"small-1024x120x20 mode={mode} path={path}")
     J, m = _inputs(g, w.n_cells, w.seed, dev)
-    polish = mode == "mixed-polish"
-    mode = "mixed" if polish else mode
-    plan = dust.Plan(g, mode, fused_kernels=2 if path == "fused2" else 1, polish=polish)
+    f32 = mode == "mixed-f32"
+    mode = "mixed" if f32 else mode
+    plan = dust.Plan(g, mode, fused_kernels=2 if path == "fused2" else 1, f32_lookup=f32)
     path = "fused" if path == "fused2" else path
     cnt = dust.new_counters(dev)
     H, T, L = _run(plan, J, m, path, cnt)
@@ -165,15 +165,15 @@ def test_zero_field_and_nan(dev, mode):
                              Lh[keep])
 
 
-@pytest.mark.parametrize("polish", [False, True])
-def test_cold_cells_use_exact_fallback(dev, polish):
+@pytest.mark.parametrize("f32", [False, True])
+def test_cold_cells_use_exact_fallback(dev, f32):
     """Pairs colder than the table's 2.7 K take the exact FP64 solve."""
     g = synth.make_grid(120, 2, 10)
     p = synth.cell_params(32, 17)
     p.logw[:, :] = -22.0  # very weak fields: T well below 2.7 K for big grains
     J = synth.radiation_field(p, g.lam, device=dev)
     m = torch.ones(32, dtype=torch.float32, device=dev)
-    plan = dust.Plan(g, "mixed", polish=polish)
+    plan = dust.Plan(g, "mixed", f32_lookup=f32)
     cnt = dust.new_counters(dev)
     T, L = plan.fused(J, m, counters=cnt)
     torch.cuda.synchronize()
@@ -182,7 +182,7 @@ def test_cold_cells_use_exact_fallback(dev, polish):
     check_against_oracle(g, _host(J), np.ones(32), _host(T), _host(L))
 
 
-@pytest.mark.parametrize("mode", ["plain", "mixed", "mixed-polish"])
+@pytest.mark.parametrize("mode", ["plain", "mixed", "mixed-f32"])
 def test_hot_cells_above_table(dev, mode):
     """Fields strong enough to heat grains above the table's 3000 K: the mixed
     path solves them exactly, the plain path by Newton as everywhere."""
@@ -191,8 +191,8 @@ def test_hot_cells_above_table(dev, mode):
     p.logw[:, :] = -1.5
     J = synth.radiation_field(p, g.lam, device=dev)
     m = torch.ones(32, dtype=torch.float32, device=dev)
-    polish = mode == "mixed-polish"
-    plan = dust.Plan(g, "mixed" if polish else mode, polish=polish)
+    f32 = mode == "mixed-f32"
+    plan = dust.Plan(g, "mixed" if f32 else mode, f32_lookup=f32)
     cnt = dust.new_counters(dev)
     T, L = plan.fused(J, m, counters=cnt)
     torch.cuda.synchronize()
