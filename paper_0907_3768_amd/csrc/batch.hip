@@ -337,18 +337,43 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     }
     b->cand = best;
 
-    // Record the chosen launch once.
+    // Record the chosen launch once.  The plans' refreshes are independent:
+    // they are captured on REFRESH_STREAMS side streams forked from the
+    // capturing stream and joined before the batched kernel, so the graph
+    // holds them as parallel branches (small kernels that would otherwise
+    // run one after another).
+    constexpr int REFRESH_STREAMS = 8;
     hipStream_t cs;
+    hipStream_t side[REFRESH_STREAMS] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[REFRESH_STREAMS] = {};
     if ((e = hipStreamCreate(&cs)) != hipSuccess) { free_batch(b); return hip_error(e, "hipStreamCreate"); }
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int n_side = 0;
+    if (refresh) {
+        e = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming);
+        for (; e == hipSuccess && n_side < REFRESH_STREAMS; ++n_side) {
+            if ((e = hipStreamCreate(&side[n_side])) != hipSuccess) break;
+            if ((e = hipEventCreateWithFlags(&join_ev[n_side], hipEventDisableTiming)) != hipSuccess) {
+                ++n_side;
+                break;
+            }
+        }
+    }
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
         if (refresh) {
+            le = hipEventRecord(fork_ev, cs);
+            for (int k = 0; k < n_side && le == hipSuccess; ++k)
+                le = hipStreamWaitEvent(side[k], fork_ev, 0);
             std::vector<const dust_plan*> seen;
             for (int g = 0; g < n_grids && le == hipSuccess; ++g) {
                 if (std::find(seen.begin(), seen.end(), plans[g]) != seen.end()) continue;
+                le = launch_prepare(plans[g], side[seen.size() % n_side]);
                 seen.push_back(plans[g]);
-                le = launch_prepare(plans[g], cs);
+            }
+            for (int k = 0; k < n_side && le == hipSuccess; ++k) {
+                le = hipEventRecord(join_ev[k], side[k]);
+                if (le == hipSuccess) le = hipStreamWaitEvent(cs, join_ev[k], 0);
             }
         }
         if (le == hipSuccess) le = enqueue(b, best, cs);
@@ -356,6 +381,11 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
         if (e == hipSuccess && le != hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    for (int k = 0; k < n_side; ++k) {
+        if (join_ev[k]) (void)hipEventDestroy(join_ev[k]);
+        if (side[k]) (void)hipStreamDestroy(side[k]);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) { free_batch(b); return hip_error(e, "graph capture"); }
     if ((e = hipDeviceSynchronize()) != hipSuccess) { free_batch(b); return hip_error(e, "hipDeviceSynchronize"); }

@@ -594,7 +594,9 @@ __device__ __forceinline__ void fill_chunk_min(const float* sInvT, uint32_t* sCh
     }
 }
 
-template <int TC>
+// TC cells from sInvT rows 0..TC-1 and sChunk columns 0..TC-1 (TCS, the
+// row stride of sChunk, is the whole tile's cell count).
+template <int TC, int TCS = TC>
 __device__ __forceinline__ void emit_accumulate(const float* __restrict__ em, int NLp,
                                                 float nu, float u_wave_min,
                                                 const float* sInvT, const uint32_t* sChunk,
@@ -610,7 +612,7 @@ __device__ __forceinline__ void emit_accumulate(const float* __restrict__ em, in
         float e[EMIT_GROUP];
 #pragma unroll
         for (int g = 0; g < EMIT_GROUP; ++g) e[g] = em[(int64_t)(s + g) * NLp];
-        const uint32_t* cmrow = sChunk + (s / EMIT_GROUP) * TC;
+        const uint32_t* cmrow = sChunk + (s / EMIT_GROUP) * TCS;
 #pragma unroll
         for (int c4 = 0; c4 < TC; c4 += 4) {
             const uint4 cm4 = *reinterpret_cast<const uint4*>(cmrow + c4);
@@ -630,25 +632,24 @@ __device__ __forceinline__ void emit_accumulate(const float* __restrict__ em, in
                 if (cm >= thr_skip) continue;
                 const float it[EMIT_GROUP] = {ia[k].x, ia[k].y, ia[k].z, ia[k].w,
                                               ib[k].x, ib[k].y, ib[k].z, ib[k].w};
-                float a = acc[c4 + k];
+                // each branch updates the accumulator in place (no copy at the merge)
                 if (cm >= thr_y) {
 #pragma unroll
                     for (int g = 0; g < EMIT_GROUP; ++g)
-                        a = fmaf(e[g], __builtin_amdgcn_exp2f(nu * it[g]), a);
+                        acc[c4 + k] = fmaf(e[g], __builtin_amdgcn_exp2f(nu * it[g]), acc[c4 + k]);
                 } else if (cm >= thr_y2) {
 #pragma unroll
                     for (int g = 0; g < EMIT_GROUP; ++g) {
                         const float y = __builtin_amdgcn_exp2f(nu * it[g]);
-                        a = fmaf(e[g], fmaf(y, y, y), a);
+                        acc[c4 + k] = fmaf(e[g], fmaf(y, y, y), acc[c4 + k]);
                     }
                 } else {
 #pragma unroll
                     for (int g = 0; g < EMIT_GROUP; ++g)
-                        a = fmaf(e[g],
-                                 __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it[g])) - 1.0f),
-                                 a);
+                        acc[c4 + k] = fmaf(
+                            e[g], __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it[g])) - 1.0f),
+                            acc[c4 + k]);
                 }
-                acc[c4 + k] = a;
             }
         }
     }

@@ -82,27 +82,45 @@ __global__ __launch_bounds__(256) void planck_factor_kernel(PlanView v, double* 
 }
 
 // y[s][k] = ln sum_l W[s][l] F[k][l] (table-linear: the sum itself): FP64
-// GEMM, 16 x 16 output tile per 256-thread block, 16-wide chunks of l staged
-// in LDS.
+// GEMM on the matrix cores (v_mfma_f64_16x16x4_f64).  Each wave computes a
+// 16-grain x 16-point block; a workgroup's four waves take four consecutive
+// point blocks.  Lane (row = lane mod 16, q = lane / 16) supplies, for every
+// 32-wavelength step, wavelengths l0 + 8 q .. l0 + 8 q + 7 to both operands
+// (grain row of W, point row of F) -- contiguous 64-byte loads; MFMA t takes
+// the t-th of them (any assignment of wavelengths to k-slots gives the same
+// sum when both operands use it).  Element j of the accumulator of lane
+// (col, q) holds row q + 4 j of column col (the FP64 form interleaves rows).
 __global__ __launch_bounds__(256) void ltab_gemm_kernel(PlanView v, const double* __restrict__ F,
                                                         double* fwd) {
-    __shared__ double sW[16][17];
-    __shared__ double sF[16][17];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int k0 = blockIdx.x * 16, s0 = blockIdx.y * 16;
-    const int k = k0 + tx, s = s0 + ty;
-    double acc = 0.0;
-    for (int l0 = 0; l0 < v.NL; l0 += 16) {
-        const int ls = l0 + tx;
-        sW[ty][tx] = (s0 + ty < v.S && ls < v.NL) ? v.kdb[(int64_t)(s0 + ty) * v.NL + ls] : 0.0;
-        sF[ty][tx] = (k0 + ty < v.N && ls < v.NL) ? F[(int64_t)(k0 + ty) * v.NL + ls] : 0.0;
-        __syncthreads();
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int row = lane & 15, q = lane >> 4;
+    const int s0 = blockIdx.y * 16;
+    const int k0 = (blockIdx.x * 4 + wave) * 16;
+    const int s = s0 + row, k = k0 + row;
+    const double* wr = v.kdb + (int64_t)(s < v.S ? s : 0) * v.NL;
+    const double* fr = F + (int64_t)(k < v.N ? k : 0) * v.NL;
+    const bool s_ok = s < v.S, k_ok = k < v.N;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < v.NL; l0 += 32) {
+        double a[8], b[8];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc = fma(sW[ty][i], sF[tx][i], acc);
-        __syncthreads();
+        for (int t = 0; t < 8; ++t) {
+            const int l = l0 + 8 * q + t;
+            a[t] = (s_ok && l < v.NL) ? wr[l] : 0.0;
+            b[t] = (k_ok && l < v.NL) ? fr[l] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[t], acc, 0, 0, 0);
     }
-    if (s < v.S && k < v.N)
-        fwd[(int64_t)s * v.N + k] = (v.mode == DUST_TABLE_LINEAR) ? acc : log(acc);
+    const int kc = k0 + row;  // column of this lane's accumulator
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int sr = s0 + q + 4 * j;
+        if (sr < v.S && kc < v.N)
+            fwd[(int64_t)sr * v.N + kc] = (v.mode == DUST_TABLE_LINEAR) ? acc[j] : log(acc[j]);
+    }
 }
 
 // Table-linear: one thread per (grain, node); node j sits at
@@ -192,7 +210,7 @@ hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
     hipLaunchKernelGGL(planck_factor_kernel, gf, dim3(256), 0, st, v, p->d_F);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 g2((v.N + 15) / 16, (v.S + 15) / 16);
+    dim3 g2((v.N + 63) / 64, (v.S + 15) / 16);
     hipLaunchKernelGGL(ltab_gemm_kernel, g2, dim3(256), 0, st, v, (const double*)p->d_F, p->d_fwd);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
