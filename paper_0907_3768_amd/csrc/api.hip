@@ -100,7 +100,7 @@ void free_plan(dust_plan* p) {
     void* ptrs[] = {p->d_lam, p->d_dlam, p->d_cabs, p->d_w,   p->d_size, p->d_es,   p->d_nu,
                     p->d_hscale, p->d_hinv, p->d_gs, p->d_kf,  p->d_kb,   p->d_em,   p->d_khi,
                     p->d_klo, p->d_kdb,  p->d_c2l,  p->d_fwd, p->d_ylo,  p->d_yhi,
-                    p->d_dyinv, p->d_texp, p->d_lntab, p->d_F, p->d_kidx, p->d_invf,
+                    p->d_dyinv, p->d_texp, p->d_lntab, p->d_kidx, p->d_invf,
                     p->d_ylof, p->d_dyinvf, p->d_ku};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -232,7 +232,6 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
         ALLOC(p->d_dyinv, S);
         ALLOC(p->d_texp, p->N);
         ALLOC(p->d_lntab, 256);
-        ALLOC(p->d_F, (size_t)p->N * NL);
     }
 #undef ALLOC
 

@@ -138,6 +138,11 @@ struct dust_batch {
     unsigned int* d_counter;
     dust_counters* counters;
     int n_cu;
+    // batched refresh of the distinct plans (DUST_BATCH_REFRESH_PLANS)
+    dust::RefreshJob* d_jobs;
+    int* d_starts;  // [4][n_jobs]
+    int n_jobs;
+    int refresh_blocks[4];
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -170,6 +175,8 @@ void free_batch(dust_batch* b) {
     if (b->d_items16) (void)hipFree(b->d_items16);
     if (b->d_items32) (void)hipFree(b->d_items32);
     if (b->d_counter) (void)hipFree(b->d_counter);
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->d_starts) (void)hipFree(b->d_starts);
     delete b;
 }
 
@@ -337,55 +344,51 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     }
     b->cand = best;
 
-    // Record the chosen launch once.  The plans' refreshes are independent:
-    // they are captured on REFRESH_STREAMS side streams forked from the
-    // capturing stream and joined before the batched kernel, so the graph
-    // holds them as parallel branches (small kernels that would otherwise
-    // run one after another).
-    constexpr int REFRESH_STREAMS = 8;
-    hipStream_t cs;
-    hipStream_t side[REFRESH_STREAMS] = {};
-    hipEvent_t fork_ev = nullptr, join_ev[REFRESH_STREAMS] = {};
-    if ((e = hipStreamCreate(&cs)) != hipSuccess) { free_batch(b); return hip_error(e, "hipStreamCreate"); }
-    int n_side = 0;
+    // The plans' refreshes as four batched launches (one per stage, every
+    // distinct plan in each), then the chosen batched kernel, recorded once.
     if (refresh) {
-        e = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming);
-        for (; e == hipSuccess && n_side < REFRESH_STREAMS; ++n_side) {
-            if ((e = hipStreamCreate(&side[n_side])) != hipSuccess) break;
-            if ((e = hipEventCreateWithFlags(&join_ev[n_side], hipEventDisableTiming)) != hipSuccess) {
-                ++n_side;
-                break;
+        std::vector<const dust_plan*> uniq;
+        for (int g = 0; g < n_grids; ++g)
+            if (std::find(uniq.begin(), uniq.end(), plans[g]) == uniq.end()) uniq.push_back(plans[g]);
+        const int nj = (int)uniq.size();
+        std::vector<RefreshJob> jobs(nj);
+        std::vector<int> starts(4 * (size_t)nj);
+        int64_t total[4] = {0, 0, 0, 0};
+        for (int k = 0; k < nj; ++k) {
+            make_refresh_job(uniq[k], &jobs[k]);
+            for (int st = 0; st < 4; ++st) {
+                starts[(size_t)st * nj + k] = (int)total[st];
+                total[st] += (int64_t)jobs[k].gx[st] * jobs[k].gy[st];
             }
         }
+        for (int st = 0; st < 4; ++st) {
+            if (total[st] > INT32_MAX) { free_batch(b); return set_error(DUST_EUNSUPPORTED, "refresh grid too large"); }
+            b->refresh_blocks[st] = (int)total[st];
+        }
+        b->n_jobs = nj;
+        if ((e = hipMalloc(&b->d_jobs, sizeof(RefreshJob) * nj)) != hipSuccess ||
+            (e = hipMalloc(&b->d_starts, sizeof(int) * starts.size())) != hipSuccess ||
+            (e = hipMemcpy(b->d_jobs, jobs.data(), sizeof(RefreshJob) * nj, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(b->d_starts, starts.data(), sizeof(int) * starts.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+            free_batch(b);
+            return hip_error(e, "batched refresh tables");
+        }
     }
-    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    hipStream_t cs;
+    if ((e = hipStreamCreate(&cs)) != hipSuccess) { free_batch(b); return hip_error(e, "hipStreamCreate"); }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
         if (refresh) {
-            le = hipEventRecord(fork_ev, cs);
-            for (int k = 0; k < n_side && le == hipSuccess; ++k)
-                le = hipStreamWaitEvent(side[k], fork_ev, 0);
-            std::vector<const dust_plan*> seen;
-            for (int g = 0; g < n_grids && le == hipSuccess; ++g) {
-                if (std::find(seen.begin(), seen.end(), plans[g]) != seen.end()) continue;
-                le = launch_prepare(plans[g], side[seen.size() % n_side]);
-                seen.push_back(plans[g]);
-            }
-            for (int k = 0; k < n_side && le == hipSuccess; ++k) {
-                le = hipEventRecord(join_ev[k], side[k]);
-                if (le == hipSuccess) le = hipStreamWaitEvent(cs, join_ev[k], 0);
-            }
+            const int* starts[4];
+            for (int st = 0; st < 4; ++st) starts[st] = b->d_starts + (size_t)st * b->n_jobs;
+            le = launch_prepare_batched(b->d_jobs, starts, b->n_jobs, b->refresh_blocks, cs);
         }
         if (le == hipSuccess) le = enqueue(b, best, cs);
         e = hipStreamEndCapture(cs, &b->graph);
         if (e == hipSuccess && le != hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-    for (int k = 0; k < n_side; ++k) {
-        if (join_ev[k]) (void)hipEventDestroy(join_ev[k]);
-        if (side[k]) (void)hipStreamDestroy(side[k]);
-    }
-    if (fork_ev) (void)hipEventDestroy(fork_ev);
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) { free_batch(b); return hip_error(e, "graph capture"); }
     if ((e = hipDeviceSynchronize()) != hipSuccess) { free_batch(b); return hip_error(e, "hipDeviceSynchronize"); }

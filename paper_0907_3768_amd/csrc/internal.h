@@ -110,7 +110,6 @@ struct dust_plan {
     float *d_nu, *d_hscale, *d_hinv, *d_gs, *d_kf, *d_kb, *d_ku, *d_em;
     __bf16 *d_khi, *d_klo;
     double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv, *d_fwd, *d_texp;
-    double* d_F;  // [N][NL] Planck factors of the table temperatures
     double2* d_lntab;
     float4* d_invf;
     float *d_ylof, *d_dyinvf;
@@ -126,6 +125,27 @@ dust_status hip_error(hipError_t e, const char* what);
 
 // Kernel launchers (each in its own translation unit).
 hipError_t launch_prepare(const dust_plan* p, hipStream_t st);
+
+// Everything the four refresh stages of one plan read and write, with each
+// stage's grid (gx, gy; gy = 0 where the plan has no such stage).
+struct RefreshJob {
+    PlanView v;
+    const double *lam, *dlam, *cabs, *w;
+    const int* es;
+    int ge;
+    float *nu, *kf, *kb, *ku, *em;
+    __bf16 *khi, *klo;
+    double *kdb, *c2l, *fwd, *ylo, *yhi, *dyinv;
+    int* kidx;
+    float2* invf;
+    float *ylof, *dyinvf;
+    int gx[4], gy[4];
+};
+void make_refresh_job(const dust_plan* p, RefreshJob* j);
+// The refresh of many plans as four launches (one per stage); d_starts[k]
+// holds, per plan, the first block of its range in stage k (ascending).
+hipError_t launch_prepare_batched(const RefreshJob* d_jobs, const int* const d_starts[4],
+                                  int n_jobs, const int blocks[4], hipStream_t st);
 hipError_t launch_absorb(const PlanView& v, int64_t C, const float* J, int64_t ldj,
                          float* H, int64_t ldh, hipStream_t st);
 hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ldh,

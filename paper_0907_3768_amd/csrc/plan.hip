@@ -7,8 +7,9 @@
 //        exponent table nu = -c2 log2(e) / lam.
 //  ltab  (mixed mode): per grain, y_k = ln P'(T_k) at log-spaced T_k, in
 //        FP64, with P'(T) = sum_l K'_l B(lam_l, T) the right side of Eq. 7 in
-//        the plan's scaled units -- as an FP64 matrix product of the grains'
-//        Planck weights with the Planck factors of the table temperatures.
+//        the plan's scaled units -- as an FP64 matrix product (MFMA) of the
+//        grains' Planck weights with the Planck factors of the table
+//        temperatures, which the product computes as it goes.
 //  inv   (mixed mode): the inverse function ln T(y) and its derivative at
 //        uniform steps of y, from Newton in FP64 on the forward table's
 //        piecewise cubic, stored as FP32 pairs of nodes (one 16-byte load
@@ -22,16 +23,19 @@
 namespace dust {
 namespace {
 
-__global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __restrict__ lam,
-                                                   const double* __restrict__ dlam,
-                                                   const double* __restrict__ cabs,
-                                                   const double* __restrict__ w,
-                                                   const int* __restrict__ es, int ge,
-                                                   float* nu, float* kf, __bf16* khi,
-                                                   __bf16* klo, float* kb, float* ku, float* em,
-                                                   double* kdb, double* c2l) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
+__device__ __forceinline__ void prep_body(const RefreshJob& j, int bx, int by) {
+    const PlanView& v = j.v;
+    const double* __restrict__ lam = j.lam;
+    const double* __restrict__ dlam = j.dlam;
+    const double* __restrict__ cabs = j.cabs;
+    const double* __restrict__ w = j.w;
+    const int* __restrict__ es = j.es;
+    const int ge = j.ge;
+    float* nu = j.nu; float* kf = j.kf; float* kb = j.kb; float* ku = j.ku; float* em = j.em;
+    __bf16* khi = j.khi; __bf16* klo = j.klo;
+    double* kdb = j.kdb; double* c2l = j.c2l;
+    const int l = bx * blockDim.x + threadIdx.x;
+    const int s = by;
     if (l >= v.NLp) return;
     const int64_t o = (int64_t)s * v.NLp + l;
     // The heating weights are stored in MFMA fragment order, so that one
@@ -68,69 +72,94 @@ __global__ __launch_bounds__(256) void prep_kernel(PlanView v, const double* __r
 
 // The table is a matrix product:  P'[s,k] = sum_l W[s,l] F[k,l]  with
 // W = K' c1 lam^-5 (per grain) and F[k,l] = 1 / (exp(c2 / (lam_l T_k)) - 1)
-// (per table temperature, the same for every grain).  F takes N x NL
-// exponentials once; the product is FP64 FMA work.
+// (per table temperature, the same for every grain).
 
-// F[k][l], one thread per element.
-__global__ __launch_bounds__(256) void planck_factor_kernel(PlanView v, double* F) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    if (l >= v.NL) return;
-    const double invT = (v.mode == DUST_TABLE_LINEAR) ? 1.0 / v.texp[k]
-                                                      : exp(-(v.lnTmin + k * v.hstep));
-    F[(int64_t)k * v.NL + l] = 1.0 / expm1_pos(v.c2l[l] * invT);  // 0 once e^x overflows
-}
+// y[s][k] = ln sum_l W[s][l] F[k][l] (table-linear: the sum itself): an FP64
+// product on the matrix cores (v_mfma_f64_16x16x4_f64) whose F operand is
+// computed in registers and never stored.  Each wave owns 16 table points
+// (a workgroup's four waves take four consecutive blocks of them) and up to
+// LT_SG grain tiles of 16.  Per 32-wavelength step, lane (row = lane mod 16,
+// q = lane / 16) computes F for point row and wavelengths l0 + 8 q .. + 7
+// (eight FP64 exponentials), loads the same wavelengths of each grain tile's
+// row of W (contiguous 64 bytes) and issues eight MFMAs per tile; MFMA t
+// takes the t-th wavelength of both operands (any assignment of wavelengths
+// to k-slots gives the same sum when both operands use it).  Element j of a
+// tile's accumulator in lane (col, q) holds grain row q + 4 j of point col
+// (the FP64 form interleaves rows).
+// Grain tiles per wave: four when many plans share a launch (the product's
+// exponentials are spent once per four tiles), one for a single plan (four
+// times the waves, for a grid that would otherwise not fill the GPU).
+constexpr int LT_SG_BATCHED = 4, LT_SG_SINGLE = 1;
 
-// y[s][k] = ln sum_l W[s][l] F[k][l] (table-linear: the sum itself): FP64
-// GEMM on the matrix cores (v_mfma_f64_16x16x4_f64).  Each wave computes a
-// 16-grain x 16-point block; a workgroup's four waves take four consecutive
-// point blocks.  Lane (row = lane mod 16, q = lane / 16) supplies, for every
-// 32-wavelength step, wavelengths l0 + 8 q .. l0 + 8 q + 7 to both operands
-// (grain row of W, point row of F) -- contiguous 64-byte loads; MFMA t takes
-// the t-th of them (any assignment of wavelengths to k-slots gives the same
-// sum when both operands use it).  Element j of the accumulator of lane
-// (col, q) holds row q + 4 j of column col (the FP64 form interleaves rows).
-__global__ __launch_bounds__(256) void ltab_gemm_kernel(PlanView v, const double* __restrict__ F,
-                                                        double* fwd) {
+template <int LT_SG>
+__device__ __forceinline__ void ltab_gemm_body(const RefreshJob& j, int bx, int by) {
     typedef double f64x4 __attribute__((ext_vector_type(4)));
+    const PlanView& v = j.v;
+    double* fwd = j.fwd;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int row = lane & 15, q = lane >> 4;
-    const int s0 = blockIdx.y * 16;
-    const int k0 = (blockIdx.x * 4 + wave) * 16;
-    const int s = s0 + row, k = k0 + row;
-    const double* wr = v.kdb + (int64_t)(s < v.S ? s : 0) * v.NL;
-    const double* fr = F + (int64_t)(k < v.N ? k : 0) * v.NL;
-    const bool s_ok = s < v.S, k_ok = k < v.N;
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int k0 = (bx * 4 + wave) * 16;
+    const int sg0 = by * LT_SG * 16;
+    const int k = k0 + row;
+    const bool k_ok = k < v.N;
+    const double invT = !k_ok ? 0.0
+                        : (v.mode == DUST_TABLE_LINEAR ? 1.0 / v.texp[k]
+                                                       : exp(-(v.lnTmin + k * v.hstep)));
+    f64x4 acc[LT_SG];
+#pragma unroll
+    for (int t = 0; t < LT_SG; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
     for (int l0 = 0; l0 < v.NL; l0 += 32) {
-        double a[8], b[8];
+        double f[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int l = l0 + 8 * q + t;
-            a[t] = (s_ok && l < v.NL) ? wr[l] : 0.0;
-            b[t] = (k_ok && l < v.NL) ? fr[l] : 0.0;
+            double x = 0.0;
+            if (k_ok && l < v.NL) {
+                const double em = expm1_pos(v.c2l[l] * invT);
+                x = (em < __builtin_inf()) ? rcp_f64(em) : 0.0;  // 0 once e^x overflows
+            }
+            f[t] = x;
         }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[t], acc, 0, 0, 0);
-    }
-    const int kc = k0 + row;  // column of this lane's accumulator
+        for (int st = 0; st < LT_SG; ++st) {
+            const int s_tile = sg0 + st * 16;
+            if (s_tile >= v.S) break;  // uniform
+            const int s = s_tile + row;
+            const double* wr = v.kdb + (int64_t)(s < v.S ? s : 0) * v.NL;
+            double a[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int sr = s0 + q + 4 * j;
-        if (sr < v.S && kc < v.N)
-            fwd[(int64_t)sr * v.N + kc] = (v.mode == DUST_TABLE_LINEAR) ? acc[j] : log(acc[j]);
+            for (int t = 0; t < 8; ++t) {
+                const int l = l0 + 8 * q + t;
+                a[t] = (s < v.S && l < v.NL) ? wr[l] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                acc[st] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], f[t], acc[st], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int st = 0; st < LT_SG; ++st) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int sr = sg0 + st * 16 + q + 4 * jj;
+            if (sr < v.S && k < v.N)
+                fwd[(int64_t)sr * v.N + k] =
+                    (v.mode == DUST_TABLE_LINEAR) ? acc[st][jj] : log(acc[st][jj]);
+        }
     }
 }
 
 // Table-linear: one thread per (grain, node); node j sits at
 // ln P' = ylo + j (yhi - ylo) / (M - 1) and kidx[s][j] is the largest k in
 // [0, N-2] with ln P'_k <= that value (0 if none).
-__global__ __launch_bounds__(256) void kidx_kernel(PlanView v, const double* __restrict__ fwd,
-                                                   int* kidx, double* ylo, double* yhi,
-                                                   double* dyinv) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
+__device__ __forceinline__ void kidx_body(const RefreshJob& job, int bx, int by) {
+    const PlanView& v = job.v;
+    const double* __restrict__ fwd = job.fwd;
+    int* kidx = job.kidx;
+    double* ylo = job.ylo; double* yhi = job.yhi; double* dyinv = job.dyinv;
+    const int j = bx * blockDim.x + threadIdx.x;
+    const int s = by;
     if (j >= v.M) return;
     const int N = v.N;
     const double* P = fwd + (int64_t)s * N;
@@ -152,12 +181,13 @@ __global__ __launch_bounds__(256) void kidx_kernel(PlanView v, const double* __r
 
 // One thread per (grain, inverse node): ln T at y_j = ylo + j dy, by Newton
 // on the forward table's cubic, and dy * d ln T / dy there.
-__global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double* __restrict__ fwd,
-                                                  double* ylo, double* yhi,
-                                                  double* dyinv, float2* invf, float* ylof,
-                                                  float* dyinvf) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
+__device__ __forceinline__ void inv_body(const RefreshJob& job, int bx, int by) {
+    const PlanView& v = job.v;
+    const double* __restrict__ fwd = job.fwd;
+    double* ylo = job.ylo; double* yhi = job.yhi; double* dyinv = job.dyinv;
+    float2* invf = job.invf; float* ylof = job.ylof; float* dyinvf = job.dyinvf;
+    const int j = bx * blockDim.x + threadIdx.x;
+    const int s = by;
     if (j >= v.M) return;
     const int N = v.N;
     const double* f = fwd + (int64_t)s * N;
@@ -196,34 +226,96 @@ __global__ __launch_bounds__(256) void inv_kernel(PlanView v, const double* __re
     if (j > 0) row[2 * (j - 1) + 1] = nf;
 }
 
+// The stages of a refresh (0 prep, 2 table product, 3 inverse table or search
+// brackets; stage 1 is empty since the product computes its Planck factors
+// itself): one block of a stage's grid.
+template <int STAGE, int LT_SG>
+__device__ __forceinline__ void refresh_stage(const RefreshJob& j, int bx, int by) {
+    if constexpr (STAGE == 0) prep_body(j, bx, by);
+    else if constexpr (STAGE == 2) ltab_gemm_body<LT_SG>(j, bx, by);
+    else if (j.v.mode == DUST_TABLE_LINEAR) kidx_body(j, bx, by);
+    else inv_body(j, bx, by);
+}
+
+// One plan: the job by value, the stage's 2-D grid.
+template <int STAGE>
+__global__ __launch_bounds__(256) void refresh_kernel(RefreshJob j) {
+    refresh_stage<STAGE, LT_SG_SINGLE>(j, blockIdx.x, blockIdx.y);
+}
+
+// Many plans in one launch: the flat block index is located among the plans'
+// consecutive ranges (starts[p] = first block of plan p, ascending) and
+// unfolded into that plan's 2-D grid of x extent gx.
+template <int STAGE>
+__global__ __launch_bounds__(256) void refresh_batched_kernel(const RefreshJob* __restrict__ jobs,
+                                                              const int* __restrict__ starts,
+                                                              int n_jobs) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const RefreshJob& j = jobs[lo];
+    const int local = b - starts[lo];
+    const int gx = j.gx[STAGE];
+    refresh_stage<STAGE, LT_SG_BATCHED>(j, local % gx, local / gx);
+}
+
+template <int STAGE>
+hipError_t launch_stage(const RefreshJob& j, hipStream_t st) {
+    // the single-plan product takes one grain tile per wave
+    const int gy = (STAGE == 2) ? (j.v.S + LT_SG_SINGLE * 16 - 1) / (LT_SG_SINGLE * 16)
+                                : j.gy[STAGE];
+    hipLaunchKernelGGL(refresh_kernel<STAGE>, dim3(j.gx[STAGE], gy), dim3(256), 0, st, j);
+    return hipGetLastError();
+}
+
+template <int STAGE>
+hipError_t launch_batched_stage(const RefreshJob* d_jobs, const int* d_starts, int n_jobs,
+                                int blocks, hipStream_t st) {
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(refresh_batched_kernel<STAGE>, dim3(blocks), dim3(256), 0, st, d_jobs,
+                       d_starts, n_jobs);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
+void make_refresh_job(const dust_plan* p, RefreshJob* j) {
     const PlanView& v = p->view;
-    dim3 g1((v.NLp + 255) / 256, v.Sp);
-    hipLaunchKernelGGL(prep_kernel, g1, dim3(256), 0, st, v, p->d_lam, p->d_dlam, p->d_cabs,
-                       p->d_w, p->d_es, p->ge, p->d_nu, p->d_kf, p->d_khi, p->d_klo, p->d_kb, p->d_ku,
-                       p->d_em, p->d_kdb, p->d_c2l);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !table_mode(v.mode)) return e;
-    dim3 gf((v.NL + 255) / 256, v.N);
-    hipLaunchKernelGGL(planck_factor_kernel, gf, dim3(256), 0, st, v, p->d_F);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    dim3 g2((v.N + 63) / 64, (v.S + 15) / 16);
-    hipLaunchKernelGGL(ltab_gemm_kernel, g2, dim3(256), 0, st, v, (const double*)p->d_F, p->d_fwd);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    dim3 g3((v.M + 255) / 256, v.S);
-    if (v.mode == DUST_TABLE_LINEAR) {
-        hipLaunchKernelGGL(kidx_kernel, g3, dim3(256), 0, st, v, (const double*)p->d_fwd,
-                           p->d_kidx, p->d_ylo, p->d_yhi, p->d_dyinv);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(inv_kernel, g3, dim3(256), 0, st, v, (const double*)p->d_fwd,
-                       p->d_ylo, p->d_yhi, p->d_dyinv, reinterpret_cast<float2*>(p->d_invf),
-                       p->d_ylof, p->d_dyinvf);
-    return hipGetLastError();
+    *j = RefreshJob{};
+    j->v = v;
+    j->lam = p->d_lam; j->dlam = p->d_dlam; j->cabs = p->d_cabs; j->w = p->d_w;
+    j->es = p->d_es; j->ge = p->ge;
+    j->nu = p->d_nu; j->kf = p->d_kf; j->kb = p->d_kb; j->ku = p->d_ku; j->em = p->d_em;
+    j->khi = p->d_khi; j->klo = p->d_klo; j->kdb = p->d_kdb; j->c2l = p->d_c2l;
+    j->fwd = p->d_fwd; j->ylo = p->d_ylo; j->yhi = p->d_yhi;
+    j->dyinv = p->d_dyinv; j->kidx = p->d_kidx; j->invf = reinterpret_cast<float2*>(p->d_invf);
+    j->ylof = p->d_ylof; j->dyinvf = p->d_dyinvf;
+    const bool tab = table_mode(v.mode);
+    j->gx[0] = (v.NLp + 255) / 256;  j->gy[0] = v.Sp;
+    j->gx[1] = 1;                    j->gy[1] = 0;
+    j->gx[2] = (v.N + 63) / 64;
+    j->gy[2] = tab ? (v.S + LT_SG_BATCHED * 16 - 1) / (LT_SG_BATCHED * 16) : 0;  // batched launches
+    j->gx[3] = (v.M + 255) / 256;    j->gy[3] = tab ? v.S : 0;
+}
+
+hipError_t launch_prepare(const dust_plan* p, hipStream_t st) {
+    RefreshJob j;
+    make_refresh_job(p, &j);
+    hipError_t e = launch_stage<0>(j, st);
+    if (e != hipSuccess || !table_mode(j.v.mode)) return e;
+    if ((e = launch_stage<2>(j, st)) != hipSuccess) return e;
+    return launch_stage<3>(j, st);
+}
+
+hipError_t launch_prepare_batched(const RefreshJob* d_jobs, const int* const d_starts[4],
+                                  int n_jobs, const int blocks[4], hipStream_t st) {
+    hipError_t e;
+    if ((e = launch_batched_stage<0>(d_jobs, d_starts[0], n_jobs, blocks[0], st)) != hipSuccess) return e;
+    if ((e = launch_batched_stage<2>(d_jobs, d_starts[2], n_jobs, blocks[2], st)) != hipSuccess) return e;
+    return launch_batched_stage<3>(d_jobs, d_starts[3], n_jobs, blocks[3], st);
 }
 
 }  // namespace dust
