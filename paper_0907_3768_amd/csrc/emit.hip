@@ -30,6 +30,16 @@ __global__ __launch_bounds__(256) void emit_kernel(PlanView v, int64_t C,
     __syncthreads();
     fill_chunk_min<TC>(sInvT, sChunk, v.Sp);
     __syncthreads();
+    // Grids of at most two 64-wavelength chunks (one column of blocks): the
+    // four waves split the tile's cells as well.
+    const int nch = (v.NL + 63) >> 6;
+    if (nch <= 2) {
+        if (nch == 2)
+            emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, 2);
+        else
+            emit_cell_part<TC / 4, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, 1);
+        return;
+    }
     const int lw0 = blockIdx.y * 256 + (threadIdx.x & ~63);
     const int l = blockIdx.y * 256 + threadIdx.x;
     const bool lv = l < v.NL;

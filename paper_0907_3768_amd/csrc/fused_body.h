@@ -277,33 +277,6 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
     }
 }
 
-// Emission of a grid with nch <= 2 wavelength chunks of 64: wave w takes
-// chunk w mod nch and CW = TC nch / 4 cells starting at (w / nch) CW.
-template <int CW, int TC>
-__device__ __forceinline__ void emit_cell_part(const PlanView& v, int64_t c0, int64_t C,
-                                               const float* __restrict__ m,
-                                               float* __restrict__ L, int64_t ldl,
-                                               const float* sInvT, const uint32_t* sChunk,
-                                               int nch) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int chunk = wave % nch;
-    const int cbase = (wave / nch) * CW;
-    const int l = chunk * 64 + (threadIdx.x & 63);
-    const bool lv = l < v.NL;
-    const float nu = v.nu[lv ? l : 0];
-    const float uw = wave_u_min(v.nu, chunk * 64, v.NL);
-    float acc[CW];
-    emit_accumulate<CW, TC>(v.em + (lv ? l : 0), v.NLp, nu, uw, sInvT + cbase * v.Sp,
-                            sChunk + cbase, v.Sp, v.S, acc);
-    if (lv) {
-#pragma unroll
-        for (int cc = 0; cc < CW; ++cc) {
-            const int64_t c = c0 + cbase + cc;
-            if (c < C) L[c * ldl + l] = acc[cc] * ((m ? m[c] : 1.0f) * v.escale);
-        }
-    }
-}
-
 template <int MODE, int TC>
 __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, int64_t C,
                                                  const float* __restrict__ m,
