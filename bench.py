@@ -522,7 +522,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "cells": C, "n_lambda": NL, "n_grains": S,
                    "species": w.n_species, "sizes_per_species": w.n_sizes, "seed": w.seed,
-                   "path": "mixed: prepare + fused absorb->solve->emit (FP64 table polish)",
+                   "path": "mixed: prepare + fused absorb->solve->emit (FP64 inverse-table lookup)",
                    "parallelism": "single GPU"},
         "roofline": roof,
         "sed_cells_per_s": C / (mixed_ms * 1e-3),

@@ -65,12 +65,12 @@ typedef enum {
     DUST_PLAIN_FP32 = 0,
     /* Mixed precision: heating on BF16 MFMA with hi+lo split operands and
        FP32 accumulation; T from per-grain tables built in FP64 (ln P at
-       log-spaced T, and its inverse ln T(ln H) at uniform steps): the
-       inverse gives the start and one FP64 Newton step on the forward
-       table's piecewise cubic polishes it (relative T error about 5e-7,
-       dominated by the heating); with `f32_lookup` the inverse's cubic
-       Hermite evaluated in FP32 is the answer (about 2e-6).  Pairs outside
-       the tabulated range are solved exactly in FP64.  FP32 emission. */
+       log-spaced T, and from it the inverse ln T(ln H) at uniform steps):
+       a cubic Hermite of the inverse evaluated in FP64 between FP64 nodes
+       (interpolation error about 1e-9; relative T error about 5e-7,
+       dominated by the heating); with `f32_lookup` the same Hermite in FP32
+       from FP32 nodes (about 2e-6).  Pairs outside the tabulated range are
+       solved exactly in FP64.  FP32 emission. */
     DUST_MIXED = 1,
     /* The production variant of the temperature step (Sections 2 and 5):
        per grain, the power of Eq. 7 tabulated in FP64 at ltab_n temperatures
@@ -109,8 +109,8 @@ typedef struct {
                               then emit).  H never reaches device memory. */
     double ltab_tmin;  /* lowest tabulated T (K): mixed 2.7, table-linear 3 */
     double ltab_tmax;  /* highest tabulated T (K): mixed 3000, table-linear 1500 */
-    int32_t f32_lookup; /* mixed: nonzero replaces the FP64 polish by the FP32
-                           inverse-table lookup */
+    int32_t f32_lookup; /* mixed: nonzero replaces the FP64 inverse-table
+                           lookup by the FP32 one */
     int32_t reserved;  /* must be 0 */
 } dust_options;
 

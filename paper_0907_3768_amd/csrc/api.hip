@@ -100,7 +100,7 @@ void free_plan(dust_plan* p) {
     void* ptrs[] = {p->d_lam, p->d_dlam, p->d_cabs, p->d_w,   p->d_size, p->d_es,   p->d_nu,
                     p->d_hscale, p->d_hinv, p->d_gs, p->d_kf,  p->d_kb,   p->d_em,   p->d_khi,
                     p->d_klo, p->d_kdb,  p->d_c2l,  p->d_fwd, p->d_ylo,  p->d_yhi,
-                    p->d_dyinv, p->d_texp, p->d_lntab, p->d_kidx, p->d_invf,
+                    p->d_dyinv, p->d_texp, p->d_lntab, p->d_kidx, p->d_invd, p->d_invf,
                     p->d_ylof, p->d_dyinvf, p->d_ku};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -223,6 +223,7 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
         if (lin) {
             ALLOC(p->d_kidx, (size_t)S * p->M);
         } else {
+            ALLOC(p->d_invd, (size_t)S * p->M);
             ALLOC(p->d_invf, (size_t)S * (p->M - 1));
             ALLOC(p->d_ylof, S);
             ALLOC(p->d_dyinvf, S);
@@ -298,10 +299,10 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     v.M = p->M;
     v.lnTmin = p->lnTmin;
     v.hstep = p->hstep;
-    v.inv_hstep = 1.0 / p->hstep;
     v.texp = p->d_texp;
     v.lntab = p->d_lntab;
     v.kidx = p->d_kidx;
+    v.invd = p->d_invd;
     v.invf = p->d_invf;
     v.ylof = p->d_ylof;
     v.dyinvf = p->d_dyinvf;

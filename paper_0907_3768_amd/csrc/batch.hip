@@ -227,7 +227,7 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
         if (!p) return set_error(DUST_EINVAL, "plans[" + std::to_string(g) + "] is NULL");
         if (p->opt.mode != DUST_MIXED || p->opt.f32_lookup)
             return set_error(DUST_EUNSUPPORTED,
-                             "batched launches take DUST_MIXED plans with the FP64 polish");
+                             "batched launches take DUST_MIXED plans with the FP64 lookup");
         if (n_cells[g] < 0 || n_cells[g] > ((int64_t)1 << 36))
             return set_error(DUST_EINVAL, "n_cells out of range");
         const int64_t c = n_cells[g];

@@ -410,35 +410,46 @@ __device__ __forceinline__ int table_lookup_f32(const PlanView& v, int s, float 
 }
 
 // ---------------------------------------------------------------------------
-// Mixed solve of Eq. 7 with the FP64 polish: the FP32 lookup above gives the
-// start (ln T within about 2e-6); the grain's forward table
-// y_k = ln P'(T_k) (FP64, log-spaced T_k) gives the cubic through the four
-// points around it, on which one FP64 Newton step in the table position
-// solves y(ln T) = ln H' (the start is within a small fraction of a table
-// step, so the step leaves an error near 1e-12 of one).  Returns as
-// table_lookup_f32.
+// ln x of a positive normal FP32 value, as an FP64 value with an absolute
+// error of about 4e-8: the binary exponent enters exactly and only log2 of
+// the mantissa (in [0.5, 1)) goes through v_log_f32.  The temperature step
+// needs y = ln H' to a small absolute error (T moves by about dy / 5), which
+// the FP32 rounding of y itself (|y| up to about 80) would not give.
 // ---------------------------------------------------------------------------
-__device__ inline int table_lookup_polish(const PlanView& v, int s, float hs, float* T,
-                                          dust_counters* cnt) {
-    float t32;
-    const int st = table_lookup_f32(v, s, hs, &t32, cnt);
-    if (st != 0 || !(t32 > 0.0f) || !(t32 < INFINITY)) {
-        *T = t32;
-        return st;
+__device__ __forceinline__ double ln_normal_f32(float x) {
+    const float m = __builtin_amdgcn_frexp_mantf(x);
+    const int e = __builtin_amdgcn_frexp_expf(x);
+    return ((double)e + (double)__builtin_amdgcn_logf(m)) * LN2;
+}
+
+// ---------------------------------------------------------------------------
+// Default mixed solve of Eq. 7: the grain's inverse table ln T(y), y = ln H',
+// at uniform steps of y (no search), as a cubic Hermite evaluated in FP64
+// between the FP64 nodes around y.  With 256 nodes the interpolation error
+// is about 1e-9 in T; T leaves in FP32 as e^head (1 + tail) from the FP32
+// head of ln T and its small tail (relative error about 1.5e-7).  Returns 0
+// with *T set, or nonzero for a pair outside the table (or with a subnormal
+// H'), which the exact FP64 solve then takes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int table_lookup_f64(const PlanView& v, int s, float hs, float* T,
+                                                dust_counters* cnt) {
+    if (!(hs >= 0.0f) || __builtin_isinf(hs)) {
+        if (cnt) count(&cnt->n_nonfinite);
+        *T = __builtin_nanf("");
+        return 0;
     }
-    const int N = v.N;
-    const double* f = v.fwd + (int64_t)s * N;
-    const double y = ln_f32_value((double)hs, v.lntab);
-    const double kt = ((double)logf(t32) - v.lnTmin) * v.inv_hstep;  // position in table steps
-    int k = (int)kt;
-    k = k < 0 ? 0 : (k > N - 2 ? N - 2 : k);
-    const int j0 = stencil_start(k, N);
-    double dp;
-    const double p = cubic4(kt - j0, f[j0], f[j0 + 1], f[j0 + 2], f[j0 + 3], &dp);
-    const double pos = kt - (p - y) * rcp_f64(dp);
-    // T leaves in FP32: e^(ln T) from the FP32 head of ln T and its small
-    // tail, e^head (1 + tail), relative error about 1.5e-7
-    const double lnT = v.lnTmin + pos * v.hstep;
+    if (hs == 0.0f) { *T = 0.0f; return 0; }
+    if (hs < 1.17549435e-38f) return 1;  // subnormal
+    const double u = (ln_normal_f32(hs) - v.ylo[s]) * v.dyinv[s];
+    if (!(u >= 0.0 && u <= (double)(v.M - 1))) return 1;  // outside, or not finite
+    const int j = (int)u < v.M - 2 ? (int)u : v.M - 2;
+    const double2* g = v.invd + (int64_t)s * v.M + j;
+    const double2 g0 = g[0], g1 = g[1];
+    const double t = u - (double)j;
+    const double d = g1.x - g0.x;
+    const double c2 = 3.0 * d - 2.0 * g0.y - g1.y;
+    const double c3 = g0.y + g1.y - 2.0 * d;
+    const double lnT = g0.x + t * (g0.y + t * (c2 + t * c3));
     const float head = (float)lnT;
     *T = expf(head) * (1.0f + (float)(lnT - (double)head));
     return 0;
@@ -451,7 +462,7 @@ __device__ __forceinline__ int mixed_lookup(const PlanView& v, int s, float hs, 
     if constexpr (MODE == MODE_MIXED_F32) {
         return table_lookup_f32(v, s, hs, T, cnt);
     } else {
-        return table_lookup_polish(v, s, hs, T, cnt);
+        return table_lookup_f64(v, s, hs, T, cnt);
     }
 }
 

@@ -54,16 +54,17 @@ struct PlanView {
     const double* ylo;     // [S] y_0
     const double* yhi;     // [S] y_{N-1}
     const double* dyinv;   // [S] (M - 1) / (yhi - ylo)
-    // inverse table ln T(y) at M uniform steps of y (computed in FP64, stored
-    // in FP32): per interval j, (ln T_j, m_j, ln T_{j+1}, m_{j+1}) in one
-    // 16-byte entry, m = dy d ln T / dy
+    // inverse table ln T(y) at M uniform steps of y, computed in FP64 from
+    // the forward table: node j holds (ln T_j, m_j), m = dy d ln T / dy
+    const double2* invd;   // [S][M] FP64 nodes (default mixed lookup)
+    // the same in FP32, per interval j (ln T_j, m_j, ln T_{j+1}, m_{j+1}) in
+    // one 16-byte entry (the FP32 lookup)
     const float4* invf;    // [S][M-1]
     const float* ylof;     // [S] float(ylo)
     const float* dyinvf;   // [S] float(dyinv)
-    int f32_lookup;        // mixed: FP32 inverse-table lookup instead of the FP64 polish
+    int f32_lookup;        // mixed: FP32 inverse-table lookup instead of the FP64 one
     int N, M;
     double lnTmin, hstep;  // ln T_k = lnTmin + k hstep
-    double inv_hstep;
     const double* texp;    // [N] T_k: exp(lnTmin + k hstep) (mixed),
                            //      tmin + k tstep (table-linear)
     const double2* lntab;  // [256] (ln c_i, 1 / c_i), c_i = 1 + i / 256
@@ -111,6 +112,7 @@ struct dust_plan {
     __bf16 *d_khi, *d_klo;
     double *d_kdb, *d_c2l, *d_ylo, *d_yhi, *d_dyinv, *d_fwd, *d_texp;
     double2* d_lntab;
+    double2* d_invd;
     float4* d_invf;
     float *d_ylof, *d_dyinvf;
     int* d_kidx;  // table-linear search brackets [S][M]
@@ -137,6 +139,7 @@ struct RefreshJob {
     __bf16 *khi, *klo;
     double *kdb, *c2l, *fwd, *ylo, *yhi, *dyinv;
     int* kidx;
+    double2* invd;
     float2* invf;
     float *ylof, *dyinvf;
     int gx[4], gy[4];
@@ -151,9 +154,8 @@ hipError_t launch_absorb(const PlanView& v, int64_t C, const float* J, int64_t l
 hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ldh,
                         float* T, int64_t ldt, dust_counters* cnt, hipStream_t st);
 // Kernel forms: the public modes, plus the mixed mode with the FP32
-// inverse-table lookup in place of the FP64 polish (a separate
-// instantiation, so that it carries none of the polish's FP64 code and
-// registers).
+// inverse-table lookup in place of the FP64 one (a separate instantiation,
+// so that it carries none of the FP64 code and registers).
 constexpr int MODE_MIXED_F32 = 3;
 // Forms whose heating runs on bf16 hi+lo MFMA and whose T comes from a table.
 __host__ __device__ constexpr bool table_mode(int mode) { return mode != DUST_PLAIN_FP32; }

@@ -185,6 +185,7 @@ __device__ __forceinline__ void inv_body(const RefreshJob& job, int bx, int by) 
     const PlanView& v = job.v;
     const double* __restrict__ fwd = job.fwd;
     double* ylo = job.ylo; double* yhi = job.yhi; double* dyinv = job.dyinv;
+    double2* invd = job.invd;
     float2* invf = job.invf; float* ylof = job.ylof; float* dyinvf = job.dyinvf;
     const int j = bx * blockDim.x + threadIdx.x;
     const int s = by;
@@ -219,6 +220,7 @@ __device__ __forceinline__ void inv_body(const RefreshJob& job, int bx, int by) 
     // d lnT / dy = hstep / (dy/dx), scaled by the node spacing dy = 1/dinv
     const double lnTj = v.lnTmin + ((double)j0 + x) * v.hstep;
     const double mj = v.hstep / dp / dinv;
+    invd[(int64_t)s * v.M + j] = make_double2(lnTj, mj);
     // the FP32 entries of the two intervals this node bounds
     const float2 nf = make_float2((float)lnTj, (float)mj);
     float2* row = invf + (int64_t)s * (v.M - 1) * 2;
@@ -291,7 +293,8 @@ void make_refresh_job(const dust_plan* p, RefreshJob* j) {
     j->nu = p->d_nu; j->kf = p->d_kf; j->kb = p->d_kb; j->ku = p->d_ku; j->em = p->d_em;
     j->khi = p->d_khi; j->klo = p->d_klo; j->kdb = p->d_kdb; j->c2l = p->d_c2l;
     j->fwd = p->d_fwd; j->ylo = p->d_ylo; j->yhi = p->d_yhi;
-    j->dyinv = p->d_dyinv; j->kidx = p->d_kidx; j->invf = reinterpret_cast<float2*>(p->d_invf);
+    j->dyinv = p->d_dyinv; j->kidx = p->d_kidx; j->invd = p->d_invd;
+    j->invf = reinterpret_cast<float2*>(p->d_invf);
     j->ylof = p->d_ylof; j->dyinvf = p->d_dyinvf;
     const bool tab = table_mode(v.mode);
     j->gx[0] = (v.NLp + 255) / 256;  j->gy[0] = v.Sp;

@@ -9,8 +9,8 @@
 // leaves with coalesced stores; the Newton evaluations of the block are
 // counted with one atomic.
 // Mixed: one thread per (cell, grain) in row-major order (coalesced H and T),
-// an O(1) lookup in the grain's tables (the inverse gives the start, an FP64
-// Newton step on the forward table polishes it; or the inverse alone in FP32).
+// an O(1) lookup in the grain's inverse table ln T(ln H) (a cubic Hermite
+// in FP64 between FP64 nodes, or in FP32 with the FP32 lookup).
 // Table-linear: the same layout, a bracketed search in the grain's table of
 // powers at evenly spaced T and linear interpolation (Sections 2 and 5).
 // Every form adds the optional extra heating Q to H first.

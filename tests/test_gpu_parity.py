@@ -165,6 +165,27 @@ def test_zero_field_and_nan(dev, mode):
                              Lh[keep])
 
 
+@pytest.mark.parametrize("f32,bound", [(False, 3e-7), (True, 4e-6)])
+def test_mixed_lookup_precision(dev, f32, bound):
+    """The mixed temperature step alone: given the oracle's FP64 heating
+    rounded to FP32, T must match the oracle's root of Eq. 7 for exactly that
+    H to the lookup's own error (FP64 inverse table: interpolation ~1e-9,
+    plus FP32 rounding of T; FP32 lookup: FP32 rounding of ln H')."""
+    w = synth.WORKLOADS["small-1024x120x20"]
+    g = w.grid()
+    J, _ = _inputs(g, 512, 23, dev)
+    H64 = oracle.heating(_host(J).astype(np.float64), g.c_abs, g.dlam)
+    H32 = H64.astype(np.float32)
+    T_ref = oracle.temperature(H32.astype(np.float64), g.lam, g.dlam, g.c_abs, g.size)
+    plan = dust.Plan(g, "mixed", f32_lookup=f32)
+    cnt = dust.new_counters(dev)
+    T = plan.solve(torch.as_tensor(H32, device=dev), counters=cnt)
+    torch.cuda.synchronize()
+    err = np.abs(_host(T).astype(np.float64) / T_ref - 1.0)
+    say(f"lookup f32={f32}: max rel T err {err.max():.3g}, out of table {int(_host(cnt)[2])}")
+    assert err.max() <= bound
+
+
 @pytest.mark.parametrize("f32", [False, True])
 def test_cold_cells_use_exact_fallback(dev, f32):
     """Pairs colder than the table's 2.7 K take the exact FP64 solve."""
