@@ -30,28 +30,18 @@ __global__ __launch_bounds__(256) void emit_kernel(PlanView v, int64_t C,
     __syncthreads();
     fill_chunk_min<TC>(sInvT, sChunk, v.Sp);
     __syncthreads();
-    // Grids of at most two 64-wavelength chunks (one column of blocks): the
-    // four waves split the tile's cells as well.
-    const int nch = (v.NL + 63) >> 6;
-    if (nch <= 2) {
-        if (nch == 2)
-            emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, 2);
-        else
-            emit_cell_part<TC / 4, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, 1);
-        return;
-    }
-    const int lw0 = blockIdx.y * 256 + (threadIdx.x & ~63);
-    const int l = blockIdx.y * 256 + threadIdx.x;
-    const bool lv = l < v.NL;
-    const float nu = v.nu[lv ? l : 0];
-    float acc[TC];
-    emit_accumulate<TC>(v.em + (lv ? l : 0), v.NLp, nu, wave_u_min(v.nu, lw0, v.NL), sInvT,
-                        sChunk, v.Sp, v.S, acc);
-    if (!lv) return;
-#pragma unroll
-    for (int cc = 0; cc < TC; ++cc) {
-        const int64_t c = c0 + cc;
-        if (c < C) L[c * ldl + l] = acc[cc] * ((m ? m[c] : 1.0f) * v.escale);
+    // Workgroup column y owns the 32-wavelength blocks 8y .. 8y + 7; wave w
+    // takes blocks 8y + w and 8y + w + 4.  Grids with fewer than four blocks
+    // (NL <= 96, one column) split the tile's cells over the waves as well.
+    const int NB = (v.NL + 31) >> 5;
+    if (NB >= 4) {
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int end = (int)blockIdx.y * 8 + 8 < NB ? (int)blockIdx.y * 8 + 8 : NB;
+        emit_tile32<TC>(v, c0, C, m, L, ldl, sInvT, sChunk, (int)blockIdx.y * 8 + w, 4, end);
+    } else if (v.NL > 64) {
+        emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, 2);
+    } else {
+        emit_cell_part<TC / 4, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, 1);
     }
 }
 

@@ -291,29 +291,17 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
     uint32_t* sChunk = reinterpret_cast<uint32_t*>(sH + n);
     fill_chunk_min<TC>(sH, sChunk, v.Sp);
     __syncthreads();
-    // Grids of at most two 64-wavelength chunks would leave waves idle: the
-    // four waves then split the tile's cells as well.
-    const int nch = (v.NL + 63) >> 6;
-    if (nch <= 2) {
-        if (nch == 2)
-            emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sH, sChunk, 2);
-        else
-            emit_cell_part<TC / 4, TC>(v, c0, C, m, L, ldl, sH, sChunk, 1);
-        return;
-    }
-    for (int l0 = 0; l0 < v.NL; l0 += blockDim.x) {
-        const int l = l0 + threadIdx.x;
-        const bool lv = l < v.NL;
-        const float nu = v.nu[lv ? l : 0];
-        const float uw = wave_u_min(v.nu, l0 + (threadIdx.x & ~63), v.NL);
-        float acc[TC];
-        emit_accumulate<TC>(v.em + (lv ? l : 0), v.NLp, nu, uw, sH, sChunk, v.Sp, v.S, acc);
-        if (lv) {
-#pragma unroll
-            for (int cc = 0; cc < TC; ++cc)
-                if (c0 + cc < C)
-                    L[(c0 + cc) * ldl + l] = acc[cc] * ((m ? m[c0 + cc] : 1.0f) * v.escale);
-        }
+    // Wave w takes the 32-wavelength blocks w, w + 4, ...; grids with fewer
+    // than four blocks (NL <= 96) would leave waves idle, so there the waves
+    // split the tile's cells as well.
+    const int NB = (v.NL + 31) >> 5;
+    if (NB >= 4) {
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        emit_tile32<TC>(v, c0, C, m, L, ldl, sH, sChunk, w, 4, NB);
+    } else if (v.NL > 64) {
+        emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sH, sChunk, 2);
+    } else {
+        emit_cell_part<TC / 4, TC>(v, c0, C, m, L, ldl, sH, sChunk, 1);
     }
 }
 
