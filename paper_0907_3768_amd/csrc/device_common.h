@@ -708,48 +708,55 @@ __device__ __forceinline__ void emit_cell_part(const PlanView& v, int64_t c0, in
 
 
 // ---------------------------------------------------------------------------
-// Emission of 16 cells over one block of 32 wavelengths by one wave: lane
-// (row r = lane / 32, i = lane mod 32) takes wavelength 32 lb + i and, of
-// every pair of 8-grain groups, group 2p + r; the two rows' partial sums are
-// added across lanes at the end.  A block of 32 wavelengths spans half the
-// range of t of one of 64, so more (pair, cell) choices take a cheap form;
-// each choice still covers 8 terms per lane.  The form of a (pair, cell) is
-// chosen as in emit_accumulate from the smaller of the two groups' smallest
-// 1/T (sChunk, TCS its row stride, already offset to the first of the 16
-// cells) and the block's smallest u.  Requires 32 lb < NLp.
+// Emission of 16 cells over one block of LW = 64 / ROWS wavelengths by one
+// wave: lane (row r = lane / LW, i = lane mod LW) takes wavelength LW lb + i
+// and, of every 16 grains, grains 16p + GR r .. 16p + GR r + GR - 1
+// (GR = 16 / ROWS); the rows' partial sums are added across lanes at the end.
+// A block of fewer than 64 wavelengths spans a smaller range of t, so more
+// (16 grains, cell) choices take a cheap form.  The form is chosen as in
+// emit_accumulate, per 16 grains, from the smaller of the two 8-grain
+// groups' smallest 1/T (sChunk, TCS its row stride, already offset to the
+// first of the 16 cells) and the block's smallest u.  Requires LW lb < NLp.
 // ---------------------------------------------------------------------------
-template <int TCS>
-__device__ __forceinline__ void emit_block32(const PlanView& v, int lb, const float* sInvT,
-                                             const uint32_t* sChunk, float (&acc)[16]) {
+constexpr int EMIT_ROWS = 2;  // rows of a wave in the block emission
+
+template <int ROWS, int TCS>
+__device__ __forceinline__ void emit_block(const PlanView& v, int lb, const float* sInvT,
+                                           const uint32_t* sChunk, float (&acc)[16]) {
+    constexpr int LW = 64 / ROWS, GR = 16 / ROWS;
+    static_assert(GR % 4 == 0, "a row takes whole float4s of grains");
     const int lane = threadIdx.x & 63;
-    const int r = lane >> 5;
-    const int l = lb * 32 + (lane & 31);
+    const int r = lane / LW;
+    const int l = lb * LW + (lane % LW);
     const float nu = v.nu[l];
-    const int lw = (lb * 32 + 31 < v.NL) ? lb * 32 + 31 : v.NL - 1;
+    const int lw = (lb * LW + LW - 1 < v.NL) ? lb * LW + LW - 1 : v.NL - 1;
     const float umin = -v.nu[lw];
     const uint32_t thr_skip = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(150.0f / umin));
     const uint32_t thr_y = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(24.0f / umin));
     const uint32_t thr_y2 = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(12.0f / umin));
-    const float* emp = v.em + (int64_t)(EMIT_GROUP * r) * v.NLp + l;
-    const float* itp = sInvT + EMIT_GROUP * r;
+    const float* emp = v.em + (int64_t)(GR * r) * v.NLp + l;
+    const float* itp = sInvT + GR * r;
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) acc[cc] = 0.0f;
     for (int s = 0; s < v.S; s += 2 * EMIT_GROUP) {
-        float e[EMIT_GROUP];
+        float e[GR];
 #pragma unroll
-        for (int g = 0; g < EMIT_GROUP; ++g) e[g] = emp[(int64_t)(s + g) * v.NLp];
+        for (int g = 0; g < GR; ++g) e[g] = emp[(int64_t)(s + g) * v.NLp];
         const uint32_t* cm0 = sChunk + (s / EMIT_GROUP) * TCS;
 #pragma unroll
         for (int c4 = 0; c4 < 16; c4 += 4) {
             const uint4 a4 = *reinterpret_cast<const uint4*>(cm0 + c4);
             const uint4 b4 = *reinterpret_cast<const uint4*>(cm0 + TCS + c4);
-            float4 ia[4], ib[4];
+            float it[4][GR];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                ia[k] = *reinterpret_cast<const float4*>(itp + (c4 + k) * v.Sp + s);
-                ib[k] = *reinterpret_cast<const float4*>(itp + (c4 + k) * v.Sp + s + 4);
+#pragma unroll
+                for (int q = 0; q < GR; q += 4) {
+                    const float4 x = *reinterpret_cast<const float4*>(itp + (c4 + k) * v.Sp + s + q);
+                    it[k][q] = x.x; it[k][q + 1] = x.y; it[k][q + 2] = x.z; it[k][q + 3] = x.w;
+                }
             }
-            // uint min: a NaN group (0) forces the exact form for the pair
+            // uint min: a NaN group (0) forces the exact form for both groups
             const uint32_t cms[4] = {
                 (uint32_t)__builtin_amdgcn_readfirstlane(a4.x < b4.x ? a4.x : b4.x),
                 (uint32_t)__builtin_amdgcn_readfirstlane(a4.y < b4.y ? a4.y : b4.y),
@@ -759,66 +766,65 @@ __device__ __forceinline__ void emit_block32(const PlanView& v, int lb, const fl
             for (int k = 0; k < 4; ++k) {
                 const uint32_t cm = cms[k];
                 if (cm >= thr_skip) continue;
-                const float it[EMIT_GROUP] = {ia[k].x, ia[k].y, ia[k].z, ia[k].w,
-                                              ib[k].x, ib[k].y, ib[k].z, ib[k].w};
                 // each branch updates the accumulator in place (no copy at the merge)
                 if (cm >= thr_y) {
 #pragma unroll
-                    for (int g = 0; g < EMIT_GROUP; ++g)
-                        acc[c4 + k] = fmaf(e[g], __builtin_amdgcn_exp2f(nu * it[g]), acc[c4 + k]);
+                    for (int g = 0; g < GR; ++g)
+                        acc[c4 + k] = fmaf(e[g], __builtin_amdgcn_exp2f(nu * it[k][g]), acc[c4 + k]);
                 } else if (cm >= thr_y2) {
 #pragma unroll
-                    for (int g = 0; g < EMIT_GROUP; ++g) {
-                        const float y = __builtin_amdgcn_exp2f(nu * it[g]);
+                    for (int g = 0; g < GR; ++g) {
+                        const float y = __builtin_amdgcn_exp2f(nu * it[k][g]);
                         acc[c4 + k] = fmaf(e[g], fmaf(y, y, y), acc[c4 + k]);
                     }
                 } else {
 #pragma unroll
-                    for (int g = 0; g < EMIT_GROUP; ++g)
+                    for (int g = 0; g < GR; ++g)
                         acc[c4 + k] = fmaf(
-                            e[g], __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it[g])) - 1.0f),
+                            e[g],
+                            __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it[k][g])) - 1.0f),
                             acc[c4 + k]);
                 }
             }
         }
     }
-    // the two rows hold partial sums over different groups
+    // the rows hold partial sums over different grains
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) acc[cc] += __shfl_xor(acc[cc], 32, 64);
+    for (int off = 32; off >= LW; off >>= 1) {
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) acc[cc] += __shfl_xor(acc[cc], off, 64);
+    }
 }
 
-// SED of a tile of TC cells (a multiple of 16) over the 32-wavelength blocks
-// lb_first, lb_first + lb_step, ... < lb_end of the calling wave, from the
-// tile's LDS (sInvT [TC][Sp], sChunk [Sp/8][TC]).  Row r of the wave stores
-// the cells of parity r.
-template <int TC>
-__device__ __forceinline__ void emit_tile32(const PlanView& v, int64_t c0, int64_t C,
-                                            const float* __restrict__ m, float* __restrict__ L,
-                                            int64_t ldl, const float* sInvT,
-                                            const uint32_t* sChunk, int lb_first, int lb_step,
-                                            int lb_end) {
+// SED of a tile of TC cells (a multiple of 16) over the blocks of
+// LW = 64 / ROWS wavelengths lb_first, lb_first + lb_step, ... < lb_end of
+// the calling wave, from the tile's LDS (sInvT [TC][Sp], sChunk [Sp/8][TC]).
+// Row r of the wave stores the cells cc with cc mod ROWS = r.
+template <int ROWS, int TC>
+__device__ __forceinline__ void emit_tile(const PlanView& v, int64_t c0, int64_t C,
+                                          const float* __restrict__ m, float* __restrict__ L,
+                                          int64_t ldl, const float* sInvT, const uint32_t* sChunk,
+                                          int lb_first, int lb_step, int lb_end) {
     static_assert(TC % 16 == 0, "cells per tile must be a multiple of 16");
+    constexpr int LW = 64 / ROWS;
     const int lane = threadIdx.x & 63;
-    const int r = lane >> 5;
+    const int r = lane / LW;
     for (int lb = lb_first; lb < lb_end; lb += lb_step) {
-        const int l = lb * 32 + (lane & 31);
+        const int l = lb * LW + (lane % LW);
 #pragma unroll 1
         for (int h = 0; h < TC; h += 16) {
             float acc[16];
-            emit_block32<TC>(v, lb, sInvT + h * v.Sp, sChunk + h, acc);
-            // a branch per row keeps the accumulator indices static
+            emit_block<ROWS, TC>(v, lb, sInvT + h * v.Sp, sChunk + h, acc);
             if (l < v.NL) {
-                if (r == 0) {
+                // a branch per row keeps the accumulator indices static
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int64_t c = c0 + h + 2 * k;
-                        if (c < C) L[c * ldl + l] = acc[2 * k] * ((m ? m[c] : 1.0f) * v.escale);
-                    }
-                } else {
+                for (int rr = 0; rr < ROWS; ++rr) {
+                    if (r != rr) continue;
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int64_t c = c0 + h + 2 * k + 1;
-                        if (c < C) L[c * ldl + l] = acc[2 * k + 1] * ((m ? m[c] : 1.0f) * v.escale);
+                    for (int k = 0; k < 16 / ROWS; ++k) {
+                        const int64_t c = c0 + h + ROWS * k + rr;
+                        if (c < C)
+                            L[c * ldl + l] = acc[ROWS * k + rr] * ((m ? m[c] : 1.0f) * v.escale);
                     }
                 }
             }

@@ -30,14 +30,16 @@ __global__ __launch_bounds__(256) void emit_kernel(PlanView v, int64_t C,
     __syncthreads();
     fill_chunk_min<TC>(sInvT, sChunk, v.Sp);
     __syncthreads();
-    // Workgroup column y owns the 32-wavelength blocks 8y .. 8y + 7; wave w
-    // takes blocks 8y + w and 8y + w + 4.  Grids with fewer than four blocks
-    // (NL <= 96, one column) split the tile's cells over the waves as well.
-    const int NB = (v.NL + 31) >> 5;
+    // Workgroup column y owns the 256 wavelengths from 256y, in blocks of
+    // LW; wave w takes the column's blocks w, w + 4, ....  Grids with fewer
+    // than four blocks (one column) split the tile's cells over the waves.
+    constexpr int LW = 64 / EMIT_ROWS, BPC = 256 / LW;
+    const int NB = (v.NL + LW - 1) / LW;
     if (NB >= 4) {
         const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int end = (int)blockIdx.y * 8 + 8 < NB ? (int)blockIdx.y * 8 + 8 : NB;
-        emit_tile32<TC>(v, c0, C, m, L, ldl, sInvT, sChunk, (int)blockIdx.y * 8 + w, 4, end);
+        const int end = (int)blockIdx.y * BPC + BPC < NB ? (int)blockIdx.y * BPC + BPC : NB;
+        emit_tile<EMIT_ROWS, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, (int)blockIdx.y * BPC + w,
+                                 4, end);
     } else if (v.NL > 64) {
         emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, 2);
     } else {

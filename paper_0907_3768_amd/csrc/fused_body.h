@@ -291,13 +291,14 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
     uint32_t* sChunk = reinterpret_cast<uint32_t*>(sH + n);
     fill_chunk_min<TC>(sH, sChunk, v.Sp);
     __syncthreads();
-    // Wave w takes the 32-wavelength blocks w, w + 4, ...; grids with fewer
-    // than four blocks (NL <= 96) would leave waves idle, so there the waves
-    // split the tile's cells as well.
-    const int NB = (v.NL + 31) >> 5;
+    // Wave w takes the wavelength blocks w, w + 4, ...; grids with fewer
+    // than four blocks would leave waves idle, so there the waves split the
+    // tile's cells as well.
+    constexpr int LW = 64 / EMIT_ROWS;
+    const int NB = (v.NL + LW - 1) / LW;
     if (NB >= 4) {
         const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        emit_tile32<TC>(v, c0, C, m, L, ldl, sH, sChunk, w, 4, NB);
+        emit_tile<EMIT_ROWS, TC>(v, c0, C, m, L, ldl, sH, sChunk, w, 4, NB);
     } else if (v.NL > 64) {
         emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sH, sChunk, 2);
     } else {
