@@ -97,7 +97,27 @@ class Timer:
         return {n: float(np.mean([s.elapsed_time(e) for s, e in v])) for n, v in self.ev.items() if v}
 
 
+# GPU clocks take about 30 ms of sustained load to settle (the first 20
+# launches of the fused step average 14 % slower than the rest), so every
+# timed form first repeats its step, untimed, for this long.
+SETTLE_S = 0.15
+
+
+def settle(torch, stages, seconds):
+    t_end = time.perf_counter() + seconds
+    n = 0
+    while True:
+        for _, fn in stages:
+            fn()
+        n += 1
+        if n % 4 == 0:
+            torch.cuda.synchronize()
+            if time.perf_counter() >= t_end:
+                return
+
+
 def time_steps(torch, stages, steps, warmup):
+    settle(torch, stages, SETTLE_S)
     for _ in range(warmup):
         for _, fn in stages:
             fn()
@@ -321,7 +341,7 @@ def run_batch(args, torch, synth, dust, dev):
     src = source_hash(BATCH_SOURCES)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": mixed_ms, "higher_is_better": True,
+        "warmup": args.warmup, "settle_s": SETTLE_S, "ms_per_step": mixed_ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
         "config": {"workload": "batch-64grids", "grids": len(specs), "cells": cells,
                    "pairs": pairs, "planck_terms": terms,
@@ -514,6 +534,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_s": SETTLE_S,
         "ms_per_step": mixed_ms,
         "higher_is_better": True,
         "scaling": "weak",

@@ -72,9 +72,11 @@ __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__
 // One workgroup per work item (the hardware dispatcher hands items out in
 // list order, heaviest first).  Same tile body as the persistent kernel but
 // without its loop, which on gfx950 costs the persistent form a lot of
-// registers (values the compiler keeps live across items).
+// registers (values the compiler keeps live across items).  Resident waves
+// per SIMD as for the single-grid fused kernel: six for up to 128 grains,
+// five above.
 template <int TC, int NTW>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_item_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 6 : 5, 8))) void batch_item_kernel(
     const GridArgs* __restrict__ grids,
                                                          const int2* __restrict__ items,
                                                          int n_items, unsigned int* counter,
