@@ -9,9 +9,10 @@ namespace {
 
 // Resident waves per SIMD: six (80 VGPRs) for grids of up to 128 grains --
 // more tiles in flight keep the phases of different tiles overlapping; the
-// compiler spills a few values of the rarely taken exact fallback; measured
-// 2 % faster than five, seven 4 % slower.  Five (96 VGPRs) for more grains,
-// whose heating accumulators would spill at six.
+// compiler spills only inside the exact fallback for out-of-table pairs,
+// which tiles without such pairs branch over; measured 4 % faster than
+// five, seven slower.  Five (96 VGPRs) for more grains, whose heating
+// accumulators would spill at six.
 template <int MODE, int NTW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 6 : 5, 8))) void fused_kernel(
     PlanView v, int64_t C,

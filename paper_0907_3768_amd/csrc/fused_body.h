@@ -62,11 +62,13 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
             x[2 * i + 1] = (lrow_ok && k + 1 < v.NL) ? jl[k + 1] : 0.0f;
         }
     };
+    // this thread's first slot in a staging buffer; the other slots are
+    // constant offsets from it (lcol is even)
+    const int slot0 = BF ? (lrow * STAGE_ROW_BF16 + lcol) / 2 : (lrow * STAGE_ROW_F32 + lcol) / 2;
     auto store_j = [&](int buf, const float (&x)[NX]) {
         char* base = sStage + buf * STAGE_BUF_BYTES;
 #pragma unroll
         for (int i = 0; i < NX / 2; ++i) {
-            const int col = lcol + 32 * i;
             const float x0 = x[2 * i], x1 = x[2 * i + 1];
             if constexpr (BF) {
                 // [hi|lo][16 rows][STAGE_ROW_BF16] bf16; a pair of columns per 32-bit store
@@ -74,12 +76,12 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
                 const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
                 const bf16x2 hi = {h0, h1};
                 const bf16x2 lo = {(__bf16)(x0 - (float)h0), (__bf16)(x1 - (float)h1)};
-                bf16x2* b = reinterpret_cast<bf16x2*>(base);
-                b[(lrow * STAGE_ROW_BF16 + col) / 2] = hi;
-                b[(16 * STAGE_ROW_BF16 + lrow * STAGE_ROW_BF16 + col) / 2] = lo;
+                bf16x2* b = reinterpret_cast<bf16x2*>(base) + slot0;
+                b[16 * i] = hi;
+                b[8 * STAGE_ROW_BF16 + 16 * i] = lo;
             } else {
-                float2* b = reinterpret_cast<float2*>(base);
-                b[(lrow * STAGE_ROW_F32 + col) / 2] = make_float2(x0, x1);
+                float2* b = reinterpret_cast<float2*>(base) + slot0;
+                b[16 * i] = make_float2(x0, x1);
             }
         }
     };
