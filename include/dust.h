@@ -101,7 +101,7 @@ typedef struct {
     int32_t mode;      /* dust_mode; default DUST_PLAIN_FP32 */
     int32_t maxit;     /* plain: Newton iteration cap, default 50 */
     double tol;        /* plain: stop when |P(T)/H - 1| <= tol, default 1e-5 */
-    int32_t ltab_n;    /* table points per grain: mixed default 4096 (>= 16),
+    int32_t ltab_n;    /* table points per grain: mixed default 1024 (>= 16),
                           table-linear default 2000 (>= 16) */
     int32_t fused_kernels; /* dust_run_fused: 0 = library choice, 1 = one kernel
                               (absorb, solve and emit per cell tile), 2 = two

@@ -75,7 +75,7 @@ dust_status resolve_options(const dust_options* in, dust_options* o) {
     if (d.tol == 0.0) d.tol = 1e-5;
     if (d.ltab_n < 0 || (d.ltab_n > 0 && d.ltab_n < 16) || d.ltab_n > MAX_TABLE / 4)
         return set_error(DUST_EINVAL, "ltab_n must be 0 (default) or in [16, 16383]");
-    if (d.ltab_n == 0) d.ltab_n = lin ? 2000 : 4096;
+    if (d.ltab_n == 0) d.ltab_n = lin ? 2000 : 1024;
     if (d.fused_kernels < 0 || d.fused_kernels > 2)
         return set_error(DUST_EINVAL, "fused_kernels must be 0, 1 or 2");
     if (d.reserved != 0) return set_error(DUST_EINVAL, "dust_options.reserved must be 0");
