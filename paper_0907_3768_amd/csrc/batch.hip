@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__
         const int ty = __builtin_amdgcn_readfirstlane(items[it].y);
         const int2 w = make_int2(gx, ty);
         const GridArgs& g = grids[w.x];
-        fused_tile<DUST_MIXED, TC, NTW>(g.v, (int64_t)w.y * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L, g.ldl,
+        fused_tile<DUST_MIXED, TC, NTW, true>(g.v, (int64_t)w.y * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L, g.ldl,
                             cnt, sTile);
         // fused_tile ends with a barrier, so sItem may be overwritten now.
     }
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 
     const int gx = __builtin_amdgcn_readfirstlane(items[it].x);
     const int ty = __builtin_amdgcn_readfirstlane(items[it].y);
     const GridArgs& g = grids[gx];
-    fused_tile<DUST_MIXED, TC, NTW>(g.v, (int64_t)ty * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L,
+    fused_tile<DUST_MIXED, TC, NTW, true>(g.v, (int64_t)ty * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L,
                                     g.ldl, cnt, sTile);
     (void)counter;
 }

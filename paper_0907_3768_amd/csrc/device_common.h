@@ -720,11 +720,72 @@ __device__ __forceinline__ void emit_cell_part(const PlanView& v, int64_t c0, in
 // ---------------------------------------------------------------------------
 constexpr int EMIT_ROWS = 2;  // rows of a wave in the block emission
 
-template <int ROWS, int TCS>
+// One choice step of emit_block: the calling lane's GRr grains starting at
+// its row's first grain (emp, itp already offset to it), all 16 cells, the
+// form chosen from the smallest 1/T bits cmA[c] (and cmB[c] when given).
+template <int GRr>
+__device__ __forceinline__ void emit_step(const float* emp, int NLp, const float* itp, int Sp,
+                                          float nu, const uint32_t* cmA, const uint32_t* cmB,
+                                          uint32_t thr_skip, uint32_t thr_y, uint32_t thr_y2,
+                                          float (&acc)[16]) {
+    float e[GRr];
+#pragma unroll
+    for (int g = 0; g < GRr; ++g) e[g] = emp[(int64_t)g * NLp];
+#pragma unroll
+    for (int c4 = 0; c4 < 16; c4 += 4) {
+        uint4 a4 = *reinterpret_cast<const uint4*>(cmA + c4);
+        if (cmB) {
+            // uint min: a NaN group (0) forces the exact form for both groups
+            const uint4 b4 = *reinterpret_cast<const uint4*>(cmB + c4);
+            a4.x = a4.x < b4.x ? a4.x : b4.x;
+            a4.y = a4.y < b4.y ? a4.y : b4.y;
+            a4.z = a4.z < b4.z ? a4.z : b4.z;
+            a4.w = a4.w < b4.w ? a4.w : b4.w;
+        }
+        float it[4][GRr];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int q = 0; q < GRr; q += 4) {
+                const float4 x = *reinterpret_cast<const float4*>(itp + (c4 + k) * Sp + q);
+                it[k][q] = x.x; it[k][q + 1] = x.y; it[k][q + 2] = x.z; it[k][q + 3] = x.w;
+            }
+        }
+        const uint32_t cms[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(a4.x),
+                                 (uint32_t)__builtin_amdgcn_readfirstlane(a4.y),
+                                 (uint32_t)__builtin_amdgcn_readfirstlane(a4.z),
+                                 (uint32_t)__builtin_amdgcn_readfirstlane(a4.w)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t cm = cms[k];
+            if (cm >= thr_skip) continue;
+            // each branch updates the accumulator in place (no copy at the merge)
+            if (cm >= thr_y) {
+#pragma unroll
+                for (int g = 0; g < GRr; ++g)
+                    acc[c4 + k] = fmaf(e[g], __builtin_amdgcn_exp2f(nu * it[k][g]), acc[c4 + k]);
+            } else if (cm >= thr_y2) {
+#pragma unroll
+                for (int g = 0; g < GRr; ++g) {
+                    const float y = __builtin_amdgcn_exp2f(nu * it[k][g]);
+                    acc[c4 + k] = fmaf(e[g], fmaf(y, y, y), acc[c4 + k]);
+                }
+            } else {
+#pragma unroll
+                for (int g = 0; g < GRr; ++g)
+                    acc[c4 + k] = fmaf(
+                        e[g], __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(-(nu * it[k][g])) - 1.0f),
+                        acc[c4 + k]);
+            }
+        }
+    }
+}
+
+template <int ROWS, int TCS, bool TAIL>
 __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const float* sInvT,
                                            const uint32_t* sChunk, float (&acc)[16]) {
     constexpr int LW = 64 / ROWS, GR = 16 / ROWS;
-    static_assert(GR % 4 == 0, "a row takes whole float4s of grains");
+    static_assert(GR % 8 == 0 || GR == 4, "a row takes whole float4s of grains");
     const int lane = threadIdx.x & 63;
     const int r = lane / LW;
     const int l = lb * LW + (lane % LW);
@@ -738,7 +799,13 @@ __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const floa
     const float* itp = sInvT + GR * r;
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) acc[cc] = 0.0f;
-    for (int s = 0; s < v.S; s += 2 * EMIT_GROUP) {
+    // 16-grain steps over the groups that hold real grains; with TAIL an odd
+    // last group is left to the step below instead of being paired with
+    // padding (a separate instantiation: the tail's code alone costs the
+    // main loop registers)
+    const int G = (v.S + EMIT_GROUP - 1) / EMIT_GROUP;
+    const int s_pairs = TAIL ? (G & ~1) * EMIT_GROUP : v.S;
+    for (int s = 0; s < s_pairs; s += 2 * EMIT_GROUP) {
         float e[GR];
 #pragma unroll
         for (int g = 0; g < GR; ++g) e[g] = emp[(int64_t)(s + g) * v.NLp];
@@ -788,6 +855,15 @@ __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const floa
             }
         }
     }
+    // an odd last group: its 8 grains split over the rows, so that no row
+    // works on grains past the last group
+    if (TAIL && (G & 1)) {
+        constexpr int GT = EMIT_GROUP / ROWS;
+        const int s_row = s_pairs + GT * r;
+        emit_step<GT>(v.em + l + (int64_t)s_row * v.NLp, v.NLp, sInvT + s_row, v.Sp, nu,
+                      sChunk + (s_pairs / EMIT_GROUP) * TCS, nullptr, thr_skip, thr_y, thr_y2,
+                      acc);
+    }
     // the rows hold partial sums over different grains
 #pragma unroll
     for (int off = 32; off >= LW; off >>= 1) {
@@ -800,7 +876,7 @@ __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const floa
 // LW = 64 / ROWS wavelengths lb_first, lb_first + lb_step, ... < lb_end of
 // the calling wave, from the tile's LDS (sInvT [TC][Sp], sChunk [Sp/8][TC]).
 // Row r of the wave stores the cells cc with cc mod ROWS = r.
-template <int ROWS, int TC>
+template <int ROWS, int TC, bool TAIL>
 __device__ __forceinline__ void emit_tile(const PlanView& v, int64_t c0, int64_t C,
                                           const float* __restrict__ m, float* __restrict__ L,
                                           int64_t ldl, const float* sInvT, const uint32_t* sChunk,
@@ -814,7 +890,7 @@ __device__ __forceinline__ void emit_tile(const PlanView& v, int64_t c0, int64_t
 #pragma unroll 1
         for (int h = 0; h < TC; h += 16) {
             float acc[16];
-            emit_block<ROWS, TC>(v, lb, sInvT + h * v.Sp, sChunk + h, acc);
+            emit_block<ROWS, TC, TAIL>(v, lb, sInvT + h * v.Sp, sChunk + h, acc);
             if (l < v.NL) {
                 // a branch per row keeps the accumulator indices static
 #pragma unroll

@@ -13,7 +13,7 @@ namespace {
 
 constexpr int EMIT_TC = 16;
 
-template <int TC>
+template <int TC, bool TAIL>
 __global__ __launch_bounds__(256) void emit_kernel(PlanView v, int64_t C,
                                                    const float* __restrict__ T, int64_t ldt,
                                                    const float* __restrict__ m,
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void emit_kernel(PlanView v, int64_t C,
     if (NB >= 4) {
         const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int end = (int)blockIdx.y * BPC + BPC < NB ? (int)blockIdx.y * BPC + BPC : NB;
-        emit_tile<EMIT_ROWS, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, (int)blockIdx.y * BPC + w,
+        emit_tile<EMIT_ROWS, TC, TAIL>(v, c0, C, m, L, ldl, sInvT, sChunk, (int)blockIdx.y * BPC + w,
                                  4, end);
     } else if (v.NL > 64) {
         emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sInvT, sChunk, 2);
@@ -54,7 +54,12 @@ hipError_t launch_emit(const PlanView& v, int64_t C, const float* T, int64_t ldt
     if (C == 0) return hipSuccess;
     dim3 grid((unsigned)((C + EMIT_TC - 1) / EMIT_TC), (unsigned)((v.NL + 255) / 256));
     const size_t lds = emit_lds_bytes(EMIT_TC, v.Sp);
-    hipLaunchKernelGGL(emit_kernel<EMIT_TC>, grid, dim3(256), lds, st, v, C, T, ldt, m, L, ldl);
+    if (((v.S + EMIT_GROUP - 1) / EMIT_GROUP) & 1)
+        hipLaunchKernelGGL((emit_kernel<EMIT_TC, true>), grid, dim3(256), lds, st, v, C, T, ldt, m,
+                           L, ldl);
+    else
+        hipLaunchKernelGGL((emit_kernel<EMIT_TC, false>), grid, dim3(256), lds, st, v, C, T, ldt,
+                           m, L, ldl);
     return hipGetLastError();
 }
 

@@ -13,7 +13,9 @@ namespace {
 // which tiles without such pairs branch over; measured 4 % faster than
 // five, seven slower.  Five (96 VGPRs) for more grains, whose heating
 // accumulators would spill at six.
-template <int MODE, int NTW>
+// TAIL: the emission's odd last grain group is its own step (grids whose
+// grain count leaves an odd number of 8-grain groups).
+template <int MODE, int NTW, bool TAIL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 6 : 5, 8))) void fused_kernel(
     PlanView v, int64_t C,
                                                    const float* __restrict__ J, int64_t ldj,
@@ -22,8 +24,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 
                                                    float* __restrict__ L, int64_t ldl,
                                                    dust_counters* cnt) {
     extern __shared__ float sTile[];
-    fused_tile<MODE, FUSED_TC, NTW>(v, (int64_t)blockIdx.x * FUSED_TC, C, J, ldj, m, T, ldt, L, ldl,
-                              cnt, sTile);
+    fused_tile<MODE, FUSED_TC, NTW, TAIL>(v, (int64_t)blockIdx.x * FUSED_TC, C, J, ldj, m, T, ldt, L,
+                                          ldl, cnt, sTile);
 }
 
 // Absorb + solve only (the first of the two-kernel form): T is written once
@@ -63,7 +65,7 @@ hipError_t launch_as_ntw(const PlanView& v, int64_t C, const float* J, int64_t l
     return hipGetLastError();
 }
 
-template <int NTW>
+template <int NTW, bool TAIL>
 hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj, const float* m,
                       float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
                       hipStream_t st) {
@@ -71,18 +73,29 @@ hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj,
     const dim3 grid((unsigned)((C + FUSED_TC - 1) / FUSED_TC));
     const int km = kernel_mode(v);
     if (km == DUST_MIXED)
-        hipLaunchKernelGGL((fused_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v, C, J, ldj,
-                           m, T, ldt, L, ldl, cnt);
+        hipLaunchKernelGGL((fused_kernel<DUST_MIXED, NTW, TAIL>), grid, dim3(256), lds, st, v, C,
+                           J, ldj, m, T, ldt, L, ldl, cnt);
     else if (km == MODE_MIXED_F32)
-        hipLaunchKernelGGL((fused_kernel<MODE_MIXED_F32, NTW>), grid, dim3(256), lds, st, v, C,
-                           J, ldj, m, T, ldt, L, ldl, cnt);
+        hipLaunchKernelGGL((fused_kernel<MODE_MIXED_F32, NTW, TAIL>), grid, dim3(256), lds, st,
+                           v, C, J, ldj, m, T, ldt, L, ldl, cnt);
     else if (v.mode == DUST_TABLE_LINEAR)
-        hipLaunchKernelGGL((fused_kernel<DUST_TABLE_LINEAR, NTW>), grid, dim3(256), lds, st, v, C,
-                           J, ldj, m, T, ldt, L, ldl, cnt);
+        hipLaunchKernelGGL((fused_kernel<DUST_TABLE_LINEAR, NTW, TAIL>), grid, dim3(256), lds,
+                           st, v, C, J, ldj, m, T, ldt, L, ldl, cnt);
     else
-        hipLaunchKernelGGL((fused_kernel<DUST_PLAIN_FP32, NTW>), grid, dim3(256), lds, st, v, C, J,
-                           ldj, m, T, ldt, L, ldl, cnt);
+        hipLaunchKernelGGL((fused_kernel<DUST_PLAIN_FP32, NTW, TAIL>), grid, dim3(256), lds, st,
+                           v, C, J, ldj, m, T, ldt, L, ldl, cnt);
     return hipGetLastError();
+}
+
+template <bool TAIL>
+hipError_t launch_fused_as(const PlanView& v, int64_t C, const float* J, int64_t ldj,
+                           const float* m, float* T, int64_t ldt, float* L, int64_t ldl,
+                           dust_counters* cnt, hipStream_t st) {
+    const int ntw = (v.Sp / 16 + 3) / 4;  // grain tiles per wave in one pass
+    if (ntw <= 1) return launch_ntw<1, TAIL>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    if (ntw <= 2) return launch_ntw<2, TAIL>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    if (ntw <= 3) return launch_ntw<3, TAIL>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    return launch_ntw<4, TAIL>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);  // 4: several passes above
 }
 
 }  // namespace
@@ -91,12 +104,9 @@ hipError_t launch_fused(const PlanView& v, int64_t C, const float* J, int64_t ld
                         float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
                         hipStream_t st) {
     if (C == 0) return hipSuccess;
-    const int ntw = (v.Sp / 16 + 3) / 4;  // grain tiles per wave in one pass
-    if (ntw <= 1) return launch_ntw<1>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
-    if (ntw <= 2) return launch_ntw<2>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
-    if (ntw <= 3) return launch_ntw<3>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
-    if (ntw <= 4) return launch_ntw<4>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
-    return launch_ntw<4>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);  // several passes
+    if (((v.S + EMIT_GROUP - 1) / EMIT_GROUP) & 1)
+        return launch_fused_as<true>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
+    return launch_fused_as<false>(v, C, J, ldj, m, T, ldt, L, ldl, cnt, st);
 }
 
 hipError_t launch_absorb_solve(const PlanView& v, int64_t C, const float* J, int64_t ldj,

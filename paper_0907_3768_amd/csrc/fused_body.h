@@ -279,7 +279,7 @@ __device__ __forceinline__ void fused_solve(const PlanView& v, int64_t c0, int64
     }
 }
 
-template <int MODE, int TC>
+template <int MODE, int TC, bool TAIL>
 __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, int64_t C,
                                                  const float* __restrict__ m,
                                                  float* __restrict__ T, int64_t ldt,
@@ -300,7 +300,7 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
     const int NB = (v.NL + LW - 1) / LW;
     if (NB >= 4) {
         const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        emit_tile<EMIT_ROWS, TC>(v, c0, C, m, L, ldl, sH, sChunk, w, 4, NB);
+        emit_tile<EMIT_ROWS, TC, TAIL>(v, c0, C, m, L, ldl, sH, sChunk, w, 4, NB);
     } else if (v.NL > 64) {
         emit_cell_part<TC / 2, TC>(v, c0, C, m, L, ldl, sH, sChunk, 2);
     } else {
@@ -318,7 +318,7 @@ __host__ __device__ constexpr size_t fused_lds_bytes(int TC, int Sp) {
 // One tile of TC cells (TC a multiple of 16) starting at cell c0; lds holds
 // fused_lds_bytes(TC, Sp) bytes.  Ends with every thread past its last read
 // of the tile's LDS.
-template <int MODE, int TC, int NTW>
+template <int MODE, int TC, int NTW, bool TAIL>
 __device__ __forceinline__ void fused_tile(const PlanView& v, int64_t c0, int64_t C,
                                            const float* __restrict__ J, int64_t ldj,
                                            const float* __restrict__ m, float* __restrict__ T,
@@ -330,7 +330,7 @@ __device__ __forceinline__ void fused_tile(const PlanView& v, int64_t c0, int64_
     for (int mb = 0; mb < TC / 16; ++mb)
         fused_absorb<MODE, NTW>(v, c0 + 16 * mb, C, J, ldj, sH + 16 * mb * v.Sp, sStage);
     __syncthreads();
-    fused_solve_emit<MODE, TC>(v, c0, C, m, T, ldt, L, ldl, cnt, sH);
+    fused_solve_emit<MODE, TC, TAIL>(v, c0, C, m, T, ldt, L, ldl, cnt, sH);
     __syncthreads();
 }
 
