@@ -295,6 +295,32 @@ def test_monotone_in_J(dev, mode):
     assert torch.all(T2 > T1)
 
 
+@pytest.mark.parametrize("mode", ["mixed", "table"])
+def test_step_graph_replays_match_eager(dev, mode):
+    """prepare + fused captured into a HIP graph (as the benchmark replays its
+    step): every replay, with eager work and synchronisation between them,
+    reproduces the eager launch bit for bit."""
+    w = synth.WORKLOADS["small-1024x120x20"]
+    g = w.grid()
+    J, m = _inputs(g, w.n_cells, w.seed, dev)
+    plan = dust.Plan(g, mode)
+    T0, L0 = plan.fused(J, m)
+    torch.cuda.synchronize()
+    T = torch.empty_like(T0)
+    L = torch.empty_like(L0)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.prepare()
+        plan.fused(J, m, T, L)
+    for rep in range(3):
+        T.fill_(-1.0)
+        L.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(T, T0) and torch.equal(L, L0), f"replay {rep}"
+
+
 @pytest.mark.parametrize("mode", ["plain", "mixed"])
 def test_deterministic_and_prepare(dev, mode):
     w = synth.WORKLOADS["small-1024x120x20"]
