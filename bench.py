@@ -568,6 +568,23 @@ def main():
     q_ms, q_k = time_steps(torch, q_stages, args.steps, args.warmup)
     del Q
 
+    # The step with J coming from, and T and L going back to, pinned host
+    # memory (what the paper's "GPU" timing included): context, never `value`.
+    log("timing the mixed step with host transfers")
+    J_host = torch.empty((C, NL), dtype=torch.float32, pin_memory=True)
+    T_host = torch.empty((C, S), dtype=torch.float32, pin_memory=True)
+    L_host = torch.empty((C, NL), dtype=torch.float32, pin_memory=True)
+    J_host.copy_(J)
+    J_dev = torch.empty_like(J)
+    xfer_stages = [("h2d_J", lambda: J_dev.copy_(J_host, non_blocking=True)),
+                   ("prepare", lambda: pm.prepare()),
+                   ("fused", lambda: pm.fused(J_dev, m, T, L, counters=cnt)),
+                   ("d2h_T_L", lambda: (T_host.copy_(T, non_blocking=True),
+                                        L_host.copy_(L, non_blocking=True)))]
+    xfer_ms, xfer_k = time_steps(torch, xfer_stages, args.steps, args.warmup)
+    xfer_bytes = 4 * (C * NL + C * S + C * NL)
+    del J_host, T_host, L_host, J_dev
+
     log("timing the table-linear mode")
     table_leg = run_table_leg(torch, dust, grid, params, J, m, T, L, cnt, args.steps, args.warmup)
 
@@ -584,8 +601,21 @@ def main():
                        "emit_Gterm_per_s": terms / (plain_k["emit"] * 1e-3) / 1e9},
         "mixed_fused_two_kernels": {"ms_per_step": f2_ms, "stages_ms": f2_k,
                                     "value": pairs / (f2_ms * 1e-3)},
-        "mixed_three_launches": {"ms_per_step": sep_ms, "stages_ms": sep_k,
-                                 "value": pairs / (sep_ms * 1e-3)},
+        "mixed_three_launches": {
+            "ms_per_step": sep_ms, "stages_ms": sep_k, "value": pairs / (sep_ms * 1e-3),
+            # each stage against the roofline that bounds it
+            "stage_roofline": {
+                "absorb": {"bound": "hbm", "GBps": 4.0 * (C * NL + C * S) / (sep_k["absorb"] * 1e-3) / 1e9,
+                           "frac": 4.0 * (C * NL + C * S) / (sep_k["absorb"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                "solve": {"bound": "latency/FP64 VALU", "pairs_per_s": pairs / (sep_k["solve"] * 1e-3),
+                          "hbm_frac": 8.0 * C * S / (sep_k["solve"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                "emit": {"bound": "alu", "Gterm_per_s": terms / (sep_k["emit"] * 1e-3) / 1e9,
+                         "frac": terms / (sep_k["emit"] * 1e-3) / TERM_PEAK_PER_S,
+                         "hbm_frac": 4.0 * (C * S + C * NL) / (sep_k["emit"] * 1e-3) / 1e9 / HBM_PEAK_GBS}}},
+        "transfer_inclusive": {"ms_per_step": xfer_ms, "stages_ms": xfer_k,
+                               "value": pairs / (xfer_ms * 1e-3), "pcie_bytes": xfer_bytes,
+                               "note": "J host->device and T, L device->host from pinned memory "
+                                       "around the step; context for the paper's GPU column"},
         "mixed_f32_lookup": {"ms_per_step": f32_ms, "stages_ms": f32_k,
                              "value": pairs / (f32_ms * 1e-3), "errors": f32_err},
         "mixed_with_extra_heating": {"ms_per_step": q_ms, "stages_ms": q_k,
