@@ -387,6 +387,33 @@ def run_batch(args, torch, synth, dust, dev):
     return 0 if ok else 3
 
 
+def run_alu_probe():
+    """Rates of the vector ALU forms the kernels are built from, per second and
+    per SIMD cycle at the 2.4 GHz peak clock (256 CUs x 4 SIMDs)."""
+    import torch
+    import paper_0907_3768_amd as dust
+    blocks, iters, chains = 256 * 16, 4096, 8
+    out = torch.empty(256 * blocks, dtype=torch.float32, device="cuda:0")
+    res = {}
+    for name, kind in (("exp2", dust.PROBE_EXP2), ("rcp", dust.PROBE_RCP), ("fma", dust.PROBE_FMA),
+                       ("exp2+fma", dust.PROBE_EXP2_FMA), ("term", dust.PROBE_TERM)):
+        dust.probe_alu(kind, blocks, iters, out)  # warm-up
+        settle(torch, [("probe", lambda: dust.probe_alu(kind, blocks, 64, out))], 0.1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dust.probe_alu(kind, blocks, iters, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        steps = 256.0 * blocks * iters * chains  # lane-steps
+        wave_instr_per_s = steps / 64.0 / (ms * 1e-3)
+        res[name] = {"ms": ms, "lane_steps_per_s": steps / (ms * 1e-3),
+                     "cycles_per_wave_step_at_2.4GHz": 1024 * 2.4e9 / wave_instr_per_s}
+    print(json.dumps({"alu_probe": res, "blocks": blocks, "iters": iters, "chains": chains}),
+          flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -398,6 +425,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--alu-probe", action="store_true",
+                    help="only run the ALU throughput probes (v_exp_f32, v_rcp_f32, v_fma_f32, "
+                         "exp + independent fma, the exact emission term) and print their rates")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline form (for kernel-trace statistics of its "
                          "kernel alone); no secondary forms and no CPU baseline")
@@ -417,6 +447,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
         return 0
+
+    if args.alu_probe:
+        return run_alu_probe()
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "

@@ -241,6 +241,32 @@ dust_status dust_batch_info(const dust_batch* batch, int32_t* cells_per_tile,
 
 dust_status dust_batch_destroy(dust_batch* batch);
 
+/* --- Measurement ----------------------------------------------------------
+   Throughput probes of the vector ALU forms the hot path is built from, for
+   checking the ALU peak used in roofline figures on the device at hand (not
+   part of the method).  `blocks` workgroups of 256 threads each run `iters`
+   iterations of 8 independent dependency chains of the chosen form:
+     DUST_PROBE_EXP2      v_exp_f32
+     DUST_PROBE_RCP       v_rcp_f32
+     DUST_PROBE_FMA       v_fma_f32
+     DUST_PROBE_EXP2_FMA  v_exp_f32 plus an independent v_fma_f32 per step
+                          (shows whether other VALU work issues alongside the
+                          transcendental pipe)
+     DUST_PROBE_TERM      the emission's exact Planck term (mul, exp, sub,
+                          rcp, fma)
+   and writes one float per thread to the device buffer `out` (caller-owned,
+   at least 256 * blocks floats).  Returns DUST_EINVAL for blocks or iters
+   outside [1, 2^20], a NULL `out` or an unknown kind; launches only (time it
+   with events on `stream`). */
+enum {
+    DUST_PROBE_EXP2 = 0,
+    DUST_PROBE_RCP = 1,
+    DUST_PROBE_FMA = 2,
+    DUST_PROBE_EXP2_FMA = 3,
+    DUST_PROBE_TERM = 4
+};
+dust_status dust_probe_alu(int32_t kind, int32_t blocks, int32_t iters, float* out, void* stream);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* dust_last_error(void);
 

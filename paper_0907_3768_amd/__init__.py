@@ -93,6 +93,7 @@ def lib():
         "dust_batch_launch": [_vp, _vp],
         "dust_batch_info": [_vp, _vp, _vp],
         "dust_batch_destroy": [_vp],
+        "dust_probe_alu": [_i32, _i32, _i32, _vp, _vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -100,6 +101,19 @@ def lib():
         f.argtypes = args
     _lib = L
     return L
+
+
+# ALU throughput probes (dust_probe_alu kinds).
+PROBE_EXP2, PROBE_RCP, PROBE_FMA, PROBE_EXP2_FMA, PROBE_TERM = 0, 1, 2, 3, 4
+
+
+def probe_alu(kind, blocks, iters, out, stream=None):
+    """Launch one ALU throughput probe; `out` is a float32 device tensor of at
+    least 256 * blocks elements (one value per thread)."""
+    if out.numel() < 256 * blocks or out.dtype.itemsize != 4 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of at least 256 * blocks elements")
+    _check(lib().dust_probe_alu(int(kind), int(blocks), int(iters), _vp(out.data_ptr()),
+                                _stream(stream)))
 
 
 def last_error() -> str:

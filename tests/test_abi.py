@@ -168,3 +168,26 @@ def test_binding_constants_match_header():
     assert len(re.findall(r"int64_t\s+n_\w+;", body)) == dust.N_COUNTERS
     ext = re.search(r"typedef struct \{(.*?)\} dust_solve_ext;", text, re.S).group(1)
     assert ctypes.sizeof(dust.SolveExt) == 24 and "warm_start" in ext and "ldq" in ext
+
+
+@pytest.mark.parametrize("kind,blocks,iters,null_out", [
+    (0, 0, 16, False),         # no blocks
+    (0, 1 << 21, 16, False),   # too many blocks
+    (1, 4, 0, False),          # no iterations
+    (2, 4, 16, True),          # NULL output
+    (9, 4, 16, False),         # unknown kind
+    (-1, 4, 16, False),
+])
+def test_probe_alu_rejects(L, kind, blocks, iters, null_out):
+    """The ALU probe checks its arguments before any HIP call."""
+    out = None if null_out else ctypes.c_void_p(16)  # never dereferenced: the call fails first
+    code = L.dust_probe_alu(kind, blocks, iters, out, None)
+    assert code == dust.DUST_EINVAL
+    assert L.dust_last_error()
+
+
+def test_binding_probe_constants_match_header():
+    text = open(os.path.join(ROOT, "include", "dust.h")).read()
+    for name, value in (("EXP2", 0), ("RCP", 1), ("FMA", 2), ("EXP2_FMA", 3), ("TERM", 4)):
+        assert re.search(rf"DUST_PROBE_{name} = {value}\b", text)
+        assert getattr(dust, f"PROBE_{name}") == value
