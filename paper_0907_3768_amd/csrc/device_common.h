@@ -584,10 +584,11 @@ __device__ __forceinline__ bool any_nan8(const float4& a, const float4& b) {
            __builtin_isnan(b.z) || __builtin_isnan(b.w);
 }
 
-// LDS bytes of an emission tile of TC cells: sInvT plus sChunk.
+// LDS bytes of an emission tile of TC cells: sInvT, sChunk and sPair.
 __host__ __device__ constexpr size_t emit_lds_bytes(int TC, int Sp) {
     return (size_t)TC * (size_t)Sp * sizeof(float) +
-           (size_t)(Sp / EMIT_GROUP) * TC * sizeof(uint32_t);
+           (size_t)(Sp / EMIT_GROUP) * TC * sizeof(uint32_t) +
+           (size_t)(Sp / (2 * EMIT_GROUP)) * TC * sizeof(uint32_t);
 }
 
 // Fill sChunk from sInvT (all threads of the block; caller synchronises).
@@ -602,6 +603,22 @@ __device__ __forceinline__ void fill_chunk_min(const float* sInvT, uint32_t* sCh
                               fminf(fminf(b.x, b.y), fminf(b.z, b.w)));
         // a NaN forces the exact form, which propagates it
         sChunk[i] = any_nan8(a, b) ? 0u : __float_as_uint(m);
+    }
+    // sPair [Sp/16][TC], right after sChunk: the same over each 16 grains
+    // (a pair of groups), for the block emission's choices
+    uint32_t* sPair = sChunk + SC * TC;
+    for (int i = threadIdx.x; i < TC * (SC / 2); i += blockDim.x) {
+        const int pr = i / TC, cc = i - pr * TC;
+        const float* row = sInvT + cc * Sp + 2 * EMIT_GROUP * pr;
+        const float4 a = *reinterpret_cast<const float4*>(row);
+        const float4 b = *reinterpret_cast<const float4*>(row + 4);
+        const float4 c = *reinterpret_cast<const float4*>(row + 8);
+        const float4 d = *reinterpret_cast<const float4*>(row + 12);
+        const float m = fminf(fminf(fminf(fminf(a.x, a.y), fminf(a.z, a.w)),
+                                    fminf(fminf(b.x, b.y), fminf(b.z, b.w))),
+                              fminf(fminf(fminf(c.x, c.y), fminf(c.z, c.w)),
+                                    fminf(fminf(d.x, d.y), fminf(d.z, d.w))));
+        sPair[i] = (any_nan8(a, b) || any_nan8(c, d)) ? 0u : __float_as_uint(m);
     }
 }
 
@@ -714,9 +731,10 @@ __device__ __forceinline__ void emit_cell_part(const PlanView& v, int64_t c0, in
 // (GR = 16 / ROWS); the rows' partial sums are added across lanes at the end.
 // A block of fewer than 64 wavelengths spans a smaller range of t, so more
 // (16 grains, cell) choices take a cheap form.  The form is chosen as in
-// emit_accumulate, per 16 grains, from the smaller of the two 8-grain
-// groups' smallest 1/T (sChunk, TCS its row stride, already offset to the
-// first of the 16 cells) and the block's smallest u.  Requires LW lb < NLp.
+// emit_accumulate, per 16 grains, from their smallest 1/T (sPair; the odd
+// last group of TAIL from sChunk; TCS the row stride of both, already offset
+// to the first of the 16 cells) and the block's smallest u.  Requires
+// LW lb < NLp.
 // ---------------------------------------------------------------------------
 constexpr int EMIT_ROWS = 2;  // rows of a wave in the block emission
 
@@ -783,7 +801,8 @@ __device__ __forceinline__ void emit_step(const float* emp, int NLp, const float
 
 template <int ROWS, int TCS, bool TAIL>
 __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const float* sInvT,
-                                           const uint32_t* sChunk, float (&acc)[16]) {
+                                           const uint32_t* sChunk, const uint32_t* sPair,
+                                           float (&acc)[16]) {
     constexpr int LW = 64 / ROWS, GR = 16 / ROWS;
     static_assert(GR % 8 == 0 || GR == 4, "a row takes whole float4s of grains");
     const int lane = threadIdx.x & 63;
@@ -809,11 +828,10 @@ __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const floa
         float e[GR];
 #pragma unroll
         for (int g = 0; g < GR; ++g) e[g] = emp[(int64_t)(s + g) * v.NLp];
-        const uint32_t* cm0 = sChunk + (s / EMIT_GROUP) * TCS;
+        const uint32_t* cmp = sPair + (s / (2 * EMIT_GROUP)) * TCS;
 #pragma unroll
         for (int c4 = 0; c4 < 16; c4 += 4) {
-            const uint4 a4 = *reinterpret_cast<const uint4*>(cm0 + c4);
-            const uint4 b4 = *reinterpret_cast<const uint4*>(cm0 + TCS + c4);
+            const uint4 a4 = *reinterpret_cast<const uint4*>(cmp + c4);
             float it[4][GR];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -823,12 +841,10 @@ __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const floa
                     it[k][q] = x.x; it[k][q + 1] = x.y; it[k][q + 2] = x.z; it[k][q + 3] = x.w;
                 }
             }
-            // uint min: a NaN group (0) forces the exact form for both groups
-            const uint32_t cms[4] = {
-                (uint32_t)__builtin_amdgcn_readfirstlane(a4.x < b4.x ? a4.x : b4.x),
-                (uint32_t)__builtin_amdgcn_readfirstlane(a4.y < b4.y ? a4.y : b4.y),
-                (uint32_t)__builtin_amdgcn_readfirstlane(a4.z < b4.z ? a4.z : b4.z),
-                (uint32_t)__builtin_amdgcn_readfirstlane(a4.w < b4.w ? a4.w : b4.w)};
+            const uint32_t cms[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(a4.x),
+                                     (uint32_t)__builtin_amdgcn_readfirstlane(a4.y),
+                                     (uint32_t)__builtin_amdgcn_readfirstlane(a4.z),
+                                     (uint32_t)__builtin_amdgcn_readfirstlane(a4.w)};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t cm = cms[k];
@@ -874,7 +890,8 @@ __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const floa
 
 // SED of a tile of TC cells (a multiple of 16) over the blocks of
 // LW = 64 / ROWS wavelengths lb_first, lb_first + lb_step, ... < lb_end of
-// the calling wave, from the tile's LDS (sInvT [TC][Sp], sChunk [Sp/8][TC]).
+// the calling wave, from the tile's LDS (sInvT [TC][Sp], then sChunk [Sp/8][TC]
+// and sPair [Sp/16][TC] as fill_chunk_min writes them).
 // Row r of the wave stores the cells cc with cc mod ROWS = r.
 template <int ROWS, int TC, bool TAIL>
 __device__ __forceinline__ void emit_tile(const PlanView& v, int64_t c0, int64_t C,
@@ -885,12 +902,13 @@ __device__ __forceinline__ void emit_tile(const PlanView& v, int64_t c0, int64_t
     constexpr int LW = 64 / ROWS;
     const int lane = threadIdx.x & 63;
     const int r = lane / LW;
+    const uint32_t* sPair = sChunk + (v.Sp / EMIT_GROUP) * TC;
     for (int lb = lb_first; lb < lb_end; lb += lb_step) {
         const int l = lb * LW + (lane % LW);
 #pragma unroll 1
         for (int h = 0; h < TC; h += 16) {
             float acc[16];
-            emit_block<ROWS, TC, TAIL>(v, lb, sInvT + h * v.Sp, sChunk + h, acc);
+            emit_block<ROWS, TC, TAIL>(v, lb, sInvT + h * v.Sp, sChunk + h, sPair + h, acc);
             if (l < v.NL) {
                 // a branch per row keeps the accumulator indices static
 #pragma unroll
