@@ -622,6 +622,14 @@ __device__ __forceinline__ void fill_chunk_min(const float* sInvT, uint32_t* sCh
     }
 }
 
+// 1/u_min for the thresholds on 1/T (t >= t0 <=> 1/T >= t0 / u_min), with
+// v_rcp_f32 instead of a correctly rounded division and a relative margin
+// of 2^-20 that only raises the thresholds, so that each form keeps its
+// guarantee (its rounding error is far below the margin).
+__device__ __forceinline__ float emit_threshold_scale(float u_min) {
+    return __builtin_amdgcn_rcpf(u_min) * (1.0f + 0x1p-20f);
+}
+
 // TC cells from sInvT rows 0..TC-1 and sChunk columns 0..TC-1 (TCS, the
 // row stride of sChunk, is the whole tile's cell count).
 template <int TC, int TCS = TC>
@@ -631,9 +639,10 @@ __device__ __forceinline__ void emit_accumulate(const float* __restrict__ em, in
                                                 int Sp, int S, float (&acc)[TC]) {
     static_assert(TC % 4 == 0, "cells per tile must be a multiple of 4");
     // Thresholds on 1/T for this wave (uniform).
-    const uint32_t thr_skip = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(150.0f / u_wave_min));
-    const uint32_t thr_y = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(24.0f / u_wave_min));
-    const uint32_t thr_y2 = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(12.0f / u_wave_min));
+    const float ru = emit_threshold_scale(u_wave_min);
+    const uint32_t thr_skip = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(150.0f * ru));
+    const uint32_t thr_y = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(24.0f * ru));
+    const uint32_t thr_y2 = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(12.0f * ru));
 #pragma unroll
     for (int cc = 0; cc < TC; ++cc) acc[cc] = 0.0f;
     for (int s = 0; s < S; s += EMIT_GROUP) {
@@ -686,7 +695,8 @@ __device__ __forceinline__ void emit_accumulate(const float* __restrict__ em, in
 // 1/T as the emission tile stores it: T < 0 or NaN gives NaN (the cell's SED
 // becomes NaN), T = 0 gives +inf (the grain emits nothing).
 __device__ __forceinline__ float inv_temperature(float t) {
-    return (t >= 0.0f) ? 1.0f / t : __builtin_nanf("");
+    // v_rcp_f32 (1 ulp): 1/T only enters the FP32 emission exponent
+    return (t >= 0.0f) ? __builtin_amdgcn_rcpf(t) : __builtin_nanf("");
 }
 
 // Smallest u = -nu over the valid wavelengths of the wave that owns
@@ -811,9 +821,10 @@ __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const floa
     const float nu = v.nu[l];
     const int lw = (lb * LW + LW - 1 < v.NL) ? lb * LW + LW - 1 : v.NL - 1;
     const float umin = -v.nu[lw];
-    const uint32_t thr_skip = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(150.0f / umin));
-    const uint32_t thr_y = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(24.0f / umin));
-    const uint32_t thr_y2 = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(12.0f / umin));
+    const float ru = emit_threshold_scale(umin);
+    const uint32_t thr_skip = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(150.0f * ru));
+    const uint32_t thr_y = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(24.0f * ru));
+    const uint32_t thr_y2 = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_uint(12.0f * ru));
     const float* emp = v.em + (int64_t)(GR * r) * v.NLp + l;
     const float* itp = sInvT + GR * r;
 #pragma unroll
