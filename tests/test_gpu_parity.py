@@ -90,7 +90,8 @@ def test_small_full_compare(dev, mode, path):
 
 @pytest.mark.parametrize("mode", ["plain", "mixed"])
 @pytest.mark.parametrize("path", ["separate", "fused", "fused2"])
-@pytest.mark.parametrize("shape", [(1000, 117, 2, 7), (77, 33, 3, 5), (1, 8, 1, 1), (130, 250, 1, 17)])
+@pytest.mark.parametrize("shape", [(1000, 117, 2, 7), (77, 33, 3, 5), (1, 8, 1, 1), (130, 250, 1, 17),
+                                   (50, 80, 2, 9)])
 def test_ragged_shapes_and_strides(dev, mode, path, shape):
     C, NL, ns, nz = shape
     say(f"ragged C={C} NL={NL} species={ns} sizes={nz} mode={mode} path={path}")
