@@ -1,11 +1,12 @@
 // Cell SED, Eqs. 9-10 (Section 4.4):
 //   L[c,l] = m[c] sum_s w_s C[s,l] B(lam_l, T[c,s]).
-// A workgroup owns TC cells and 256 consecutive wavelengths; each lane owns
-// one wavelength (coalesced L stores) and TC accumulators.  The tile's 1/T
-// sits in LDS and is read with wave-uniform addresses (broadcast); the
-// emission weights em[s,l] are read once per grain and reused for TC cells.
-// Per term: one multiply, v_exp_f32, one subtract, v_rcp_f32, one multiply,
-// one FMA.
+// A workgroup owns TC cells and 256 consecutive wavelengths, in blocks of
+// 32; a wave takes one block at a time, its lanes 32 wavelengths x 2 rows of
+// grain groups, each lane 16 partial sums (emit_block), and the rows' sums
+// are added across lanes before the store.  The tile's 1/T sits in LDS; the
+// emission weights em[s,l] are read once per grain and reused for the
+// tile's cells.  An exact term is one multiply, v_exp_f32, one subtract,
+// v_rcp_f32 and one FMA.
 #include "device_common.h"
 
 namespace dust {
