@@ -86,9 +86,9 @@ __device__ __forceinline__ void prep_body(const RefreshJob& j, int bx, int by) {
 // to k-slots gives the same sum when both operands use it).  Element j of a
 // tile's accumulator in lane (col, q) holds grain row q + 4 j of point col
 // (the FP64 form interleaves rows).
-// Grain tiles per wave: four when many plans share a launch (the product's
-// exponentials are spent once per four tiles), one for a single plan (four
-// times the waves, for a grid that would otherwise not fill the GPU).
+// Grain tiles per wave when many plans share a launch: four (the product's
+// exponentials are spent once per four tiles).  A single plan takes the
+// split form below instead (LT_SG_SINGLE only instantiates the other stages).
 constexpr int LT_SG_BATCHED = 4, LT_SG_SINGLE = 1;
 
 template <int LT_SG>
@@ -146,6 +146,55 @@ __device__ __forceinline__ void ltab_gemm_body(const RefreshJob& j, int bx, int 
             if (sr < v.S && k < v.N)
                 fwd[(int64_t)sr * v.N + k] =
                     (v.mode == DUST_TABLE_LINEAR) ? acc[st][jj] : log(acc[st][jj]);
+        }
+    }
+}
+
+// The product for a single plan: a workgroup takes one block of 16 points
+// and one grain tile, its four waves split the wavelength steps (wave w
+// takes steps w, w + 4, ...) and the partial accumulators meet in LDS.  A
+// single grid has too few (point block, grain tile) pairs to fill the GPU
+// with one wave each, and each wave's chain of FP64 exponentials is then the
+// whole wavelength range.
+__device__ __forceinline__ void ltab_gemm_split_body(const RefreshJob& j, int bx, int by) {
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    __shared__ f64x4 part[3][64];
+    const PlanView& v = j.v;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int row = lane & 15, q = lane >> 4;
+    const int k = bx * 16 + row;
+    const int s = by * 16 + row;
+    const bool k_ok = k < v.N;
+    const double invT = !k_ok ? 0.0
+                        : (v.mode == DUST_TABLE_LINEAR ? 1.0 / v.texp[k]
+                                                       : exp(-(v.lnTmin + k * v.hstep)));
+    const double* wr = v.kdb + (int64_t)(s < v.S ? s : 0) * v.NL;
+    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 32 * wave; l0 < v.NL; l0 += 128) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int l = l0 + 8 * q + t;
+            double f = 0.0, a = 0.0;
+            if (l < v.NL) {
+                if (k_ok) {
+                    const double em = expm1_pos(v.c2l[l] * invT);
+                    f = (em < __builtin_inf()) ? rcp_f64(em) : 0.0;  // 0 once e^x overflows
+                }
+                if (s < v.S) a = wr[l];
+            }
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, f, acc, 0, 0, 0);
+        }
+    }
+    if (wave > 0) part[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+        acc += part[0][lane] + part[1][lane] + part[2][lane];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int sr = by * 16 + q + 4 * jj;
+            if (sr < v.S && k_ok)
+                j.fwd[(int64_t)sr * v.N + k] = (v.mode == DUST_TABLE_LINEAR) ? acc[jj] : log(acc[jj]);
         }
     }
 }
@@ -239,10 +288,14 @@ __device__ __forceinline__ void refresh_stage(const RefreshJob& j, int bx, int b
     else inv_body(j, bx, by);
 }
 
-// One plan: the job by value, the stage's 2-D grid.
+// One plan: the job by value, the stage's 2-D grid (the product in its
+// split form).
 template <int STAGE>
 __global__ __launch_bounds__(256) void refresh_kernel(RefreshJob j) {
-    refresh_stage<STAGE, LT_SG_SINGLE>(j, blockIdx.x, blockIdx.y);
+    if constexpr (STAGE == 2)
+        ltab_gemm_split_body(j, blockIdx.x, blockIdx.y);
+    else
+        refresh_stage<STAGE, LT_SG_SINGLE>(j, blockIdx.x, blockIdx.y);
 }
 
 // Many plans in one launch: the flat block index is located among the plans'
@@ -266,10 +319,10 @@ __global__ __launch_bounds__(256) void refresh_batched_kernel(const RefreshJob* 
 
 template <int STAGE>
 hipError_t launch_stage(const RefreshJob& j, hipStream_t st) {
-    // the single-plan product takes one grain tile per wave
-    const int gy = (STAGE == 2) ? (j.v.S + LT_SG_SINGLE * 16 - 1) / (LT_SG_SINGLE * 16)
-                                : j.gy[STAGE];
-    hipLaunchKernelGGL(refresh_kernel<STAGE>, dim3(j.gx[STAGE], gy), dim3(256), 0, st, j);
+    // the single-plan product: one (16-point block, grain tile) per workgroup
+    const int gx = (STAGE == 2) ? (j.v.N + 15) / 16 : j.gx[STAGE];
+    const int gy = (STAGE == 2) ? (j.v.S + 15) / 16 : j.gy[STAGE];
+    hipLaunchKernelGGL(refresh_kernel<STAGE>, dim3(gx, gy), dim3(256), 0, st, j);
     return hipGetLastError();
 }
 
