@@ -17,6 +17,8 @@ dust_status set_error(dust_status code, const std::string& msg) {
     return code;
 }
 
+void clear_error() { g_last_error.clear(); }
+
 dust_status hip_error(hipError_t e, const char* what) {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
     return set_error(e == hipErrorOutOfMemory ? DUST_ENOMEM : DUST_EDEVICE, m);

@@ -208,6 +208,7 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
                               const float* const* m_dust, float* const* T, const int64_t* ldt,
                               float* const* L, const int64_t* ldl, dust_counters* counters,
                               int32_t flags, dust_batch** out) {
+    clear_error();
     const bool autotune = (flags & DUST_BATCH_AUTOTUNE) != 0;
     const bool refresh = (flags & DUST_BATCH_REFRESH_PLANS) != 0;
     if (!out) return set_error(DUST_EINVAL, "out is NULL");
@@ -399,12 +400,14 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
 }
 
 dust_status dust_batch_launch(dust_batch* b, void* stream) {
+    clear_error();
     if (!b) return set_error(DUST_EINVAL, "batch is NULL");
     hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
     return e == hipSuccess ? DUST_OK : hip_error(e, "hipGraphLaunch");
 }
 
 dust_status dust_batch_info(const dust_batch* b, int32_t* cells_per_tile, int64_t* n_items) {
+    clear_error();
     if (!b) return set_error(DUST_EINVAL, "batch is NULL");
     if (cells_per_tile) *cells_per_tile = b->cand.tc;
     if (n_items) *n_items = b->cand.tc == 32 ? b->n_items_32 : b->n_items_16;
@@ -412,6 +415,7 @@ dust_status dust_batch_info(const dust_batch* b, int32_t* cells_per_tile, int64_
 }
 
 dust_status dust_batch_destroy(dust_batch* b) {
+    clear_error();
     if (!b) return DUST_OK;
     hipError_t e = hipDeviceSynchronize();
     free_batch(b);

@@ -123,6 +123,8 @@ namespace dust {
 
 // Thread-local error text; returns `code` for convenience.
 dust_status set_error(dust_status code, const std::string& msg);
+// Clears the calling thread's last error (every entry point starts with it).
+void clear_error();
 dust_status hip_error(hipError_t e, const char* what);
 
 // Kernel launchers (each in its own translation unit).

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(256) void probe_kernel(float* __restrict__ out, int
 extern "C" dust_status dust_probe_alu(int32_t kind, int32_t blocks, int32_t iters, float* out,
                                       void* stream) {
     using namespace dust;
+    clear_error();
     if (blocks < 1 || blocks > (1 << 20)) return set_error(DUST_EINVAL, "blocks must be in [1, 2^20]");
     if (iters < 1 || iters > (1 << 20)) return set_error(DUST_EINVAL, "iters must be in [1, 2^20]");
     if (!out) return set_error(DUST_EINVAL, "out is NULL");
