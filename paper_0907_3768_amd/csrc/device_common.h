@@ -530,7 +530,9 @@ __device__ inline float table_linear_T(const PlanView& v, int s, float hs, dust_
         if (cnt && h != pn) count(&cnt->n_out_of_table);
         return (float)(h < p0 ? v.texp[0] : v.texp[N - 1]);
     }
-    const double u = (ln_f32_value(h, v.lntab) - v.ylo[s]) * v.dyinv[s];
+    // the position only chooses the bracket (a miss falls back to the whole
+    // table), so the table-free ln of the FP32 value is enough
+    const double u = (ln_normal_f32(hs) - v.ylo[s]) * v.dyinv[s];
     const int j = (u > 0.0) ? (u < (double)(v.M - 2) ? (int)u : v.M - 2) : 0;
     const int* kx = v.kidx + (int64_t)s * v.M;
     int a = kx[j], b = kx[j + 1] + 1;  // kidx <= N - 2, so b <= N - 1
@@ -546,7 +548,7 @@ __device__ inline float table_linear_T(const PlanView& v, int s, float hs, dust_
         const double pm = P[mid];
         if (pm <= h) { a = mid; pa = pm; } else { b = mid; pb = pm; }
     }
-    return (float)(v.texp[a] + (h - pa) / (pb - pa) * v.tstep);
+    return (float)(v.texp[a] + (h - pa) * rcp_f64(pb - pa) * v.tstep);
 }
 
 // Capacity of a block's LDS list of pending pairs.
