@@ -740,7 +740,9 @@ __device__ __forceinline__ void emit_cell_part(const PlanView& v, int64_t c0, in
 // Emission of 16 cells over one block of LW = 64 / ROWS wavelengths by one
 // wave: lane (row r = lane / LW, i = lane mod LW) takes wavelength LW lb + i
 // and, of every 16 grains, grains 16p + GR r .. 16p + GR r + GR - 1
-// (GR = 16 / ROWS); the rows' partial sums are added across lanes at the end.
+// (GR = 16 / ROWS); the rows' partial sums are added across lanes at the end:
+// with two rows, row r then holds the sum of cell 2k + r in acc[2k], with
+// more rows every lane holds all 16 sums.
 // A block of fewer than 64 wavelengths spans a smaller range of t, so more
 // (16 grains, cell) choices take a cheap form.  The form is chosen as in
 // emit_accumulate, per 16 grains, from their smallest 1/T (sPair; the odd
@@ -894,10 +896,23 @@ __device__ __forceinline__ void emit_block(const PlanView& v, int lb, const floa
                       acc);
     }
     // the rows hold partial sums over different grains
+    if constexpr (ROWS == 2) {
+        // v_permlane32_swap of cells 2k and 2k + 1 leaves row 0's and row 1's
+        // partial sums of cell 2k in the two registers of lanes 0-31 and
+        // those of cell 2k + 1 in lanes 32-63: one add gives row r the sum of
+        // cell 2k + r in acc[2k], with no trip through LDS
 #pragma unroll
-    for (int off = 32; off >= LW; off >>= 1) {
+        for (int k = 0; k < 8; ++k) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(
+                __float_as_uint(acc[2 * k]), __float_as_uint(acc[2 * k + 1]), false, false);
+            acc[2 * k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+        }
+    } else {
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) acc[cc] += __shfl_xor(acc[cc], off, 64);
+        for (int off = 32; off >= LW; off >>= 1) {
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) acc[cc] += __shfl_xor(acc[cc], off, 64);
+        }
     }
 }
 
@@ -922,7 +937,21 @@ __device__ __forceinline__ void emit_tile(const PlanView& v, int64_t c0, int64_t
         for (int h = 0; h < TC; h += 16) {
             float acc[16];
             emit_block<ROWS, TC, TAIL>(v, lb, sInvT + h * v.Sp, sChunk + h, sPair + h, acc);
-            if (l < v.NL) {
+            if (l >= v.NL) continue;
+            if constexpr (ROWS == 2) {
+                // row r holds the sum of cell 2k + r in acc[2k]; the two cells'
+                // masses are wave-uniform loads (clamped to the last cell)
+                const int64_t cb = c0 + h;
+                float* Lp = L + (cb + r) * ldl + l;  // cell cb + r; cells 2k further on
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int64_t ce = cb + 2 * k < C ? cb + 2 * k : C - 1;
+                    const int64_t co = cb + 2 * k + 1 < C ? cb + 2 * k + 1 : C - 1;
+                    const float me = m ? m[ce] : 1.0f, mo = m ? m[co] : 1.0f;
+                    if (cb + 2 * k + r < C)
+                        Lp[2 * k * ldl] = acc[2 * k] * ((r ? mo : me) * v.escale);
+                }
+            } else {
                 // a branch per row keeps the accumulator indices static
 #pragma unroll
                 for (int rr = 0; rr < ROWS; ++rr) {

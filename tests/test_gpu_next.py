@@ -106,7 +106,8 @@ def test_table_never_above_exact_root(dev):
     say(f"table-linear error vs exact root: max {rel.max():.3e}  median {np.median(rel):.3e}")
 
 
-@pytest.mark.parametrize("shape", [(77, 33, 3, 5), (1, 8, 1, 1), (130, 250, 1, 17), (50, 80, 2, 9)])
+@pytest.mark.parametrize("shape", [(77, 33, 3, 5), (1, 8, 1, 1), (130, 250, 1, 17), (50, 80, 2, 9),
+                                   (45, 200, 3, 5), (70, 300, 1, 23)])
 def test_table_ragged(dev, shape):
     C, NL, ns, nz = shape
     g = synth.make_grid(NL, ns, nz)

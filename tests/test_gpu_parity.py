@@ -91,7 +91,11 @@ def test_small_full_compare(dev, mode, path):
 @pytest.mark.parametrize("mode", ["plain", "mixed"])
 @pytest.mark.parametrize("path", ["separate", "fused", "fused2"])
 @pytest.mark.parametrize("shape", [(1000, 117, 2, 7), (77, 33, 3, 5), (1, 8, 1, 1), (130, 250, 1, 17),
-                                   (50, 80, 2, 9)])
+                                   (50, 80, 2, 9),
+                                   # 5, 6 and 7 wavelength blocks of 32 (leftover blocks
+                                   # shared by cells), and 10 (a second emission column of 2)
+                                   (300, 150, 2, 6), (33, 190, 2, 4), (45, 200, 3, 5),
+                                   (70, 300, 1, 23)])
 def test_ragged_shapes_and_strides(dev, mode, path, shape):
     C, NL, ns, nz = shape
     say(f"ragged C={C} NL={NL} species={ns} sizes={nz} mode={mode} path={path}")
