@@ -15,6 +15,7 @@ import pytest
 import oracle
 import synth
 from gpu_helpers import T_TOL, check_against_oracle, oracle_on_rows, strided_rows
+from oracle.compare import sed_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -286,6 +287,48 @@ def test_sed_energy_identity_on_gpu(dev, mode):
     lhs = (_host(L).astype(np.float64) * g.dlam).sum(1)
     rhs = _host(m).astype(np.float64) * (H_ref * g.weight).sum(1)
     assert np.max(np.abs(lhs / rhs - 1)) < 1e-3
+
+
+@pytest.mark.parametrize("NL", [250, 80])
+def test_emission_forms_across_temperatures(dev, NL):
+    """Eqs. 9-10 alone, element by element, on a sweep of temperatures from 3 K
+    to 2000 K (grains of a cell within +-30 % of the cell's T), so that the
+    emission's per-(grain group, cell, wavelength block) choices fall in every
+    band of t = h c log2(e) / (k lam T) (each term is 1/(2^t - 1)): skipped,
+    y, y + y^2 and the exact form (NL = 250: blocks of 32
+    wavelengths and 16 grains; NL = 80, fewer than four blocks: chunks of 64
+    wavelengths and 8 grains).
+    Bound: t carries the rounding of u_l, 1/T and their product (<= 4 2^-24
+    relative, i.e. <= ln 2 * 4 * 2^-24 * t relative in 2^-t), each form
+    <= 2^-24 of truncation, exp2 / rcp / the weights a few ulp,
+    and the FP32 sum over S grains S 2^-24; over the elements at least 1e-6
+    of their row's peak t stays below about 40, so 2e-5 holds with room."""
+    g = synth.make_grid(NL, 2, 40)
+    C, S = 600, g.n_grains
+    rng = np.random.default_rng(11)
+    Tc = 3.0 * (2000.0 / 3.0) ** (np.arange(C) / (C - 1))
+    Th = (Tc[:, None] * rng.uniform(0.7, 1.3, size=(C, S))).astype(np.float32)
+    mh = rng.uniform(0.5, 2.0, size=C).astype(np.float32)
+    # the sweep reaches every band, with the choices taken as the kernel takes them
+    u = 6.62607015e-34 * 299792458.0 / 1.380649e-23 * math.log2(math.e) / g.lam
+    lw, gw = (32, 16) if -(-NL // 32) >= 4 else (64, 8)
+    hot = (1.0 / Th.astype(np.float64)).reshape(C, S // gw, gw).min(axis=2)
+    bands = set()
+    for b in range(-(-NL // lw)):
+        t = u[min(lw * b + lw - 1, NL - 1)] * hot
+        bands |= set(np.digitize(t.ravel(), [12.0, 24.0, 150.0]).tolist())
+    # (chunks of 64 end at long wavelengths, where no grain of the sweep is
+    # cold enough to be skipped)
+    assert bands >= ({0, 1, 2, 3} if lw == 32 else {0, 1, 2}), bands
+    plan = dust.Plan(g, "mixed")
+    T = torch.as_tensor(Th, device=dev)
+    m = torch.as_tensor(mh, device=dev)
+    L = plan.emit(T, m)
+    torch.cuda.synchronize()
+    L_ref = oracle.emission(Th, g.lam, g.c_abs, g.weight, mh)
+    err = sed_errors(_host(L), L_ref, g.dlam)
+    say(f"emission NL={NL}: {err}")
+    assert err["max"] <= 2e-5, err
 
 
 @pytest.mark.parametrize("mode", ["plain", "mixed"])
