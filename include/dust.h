@@ -40,7 +40,10 @@
  *      n_out_of_table  pairs of the mixed solve whose T lies outside the
  *                      tabulated range (solved exactly instead)
  *    H == 0 gives T = 0, and a grain at T = 0 emits nothing.
- *  - Calls that share a plan may run concurrently on different streams.
+ *  - Calls that share a plan may run concurrently on different streams,
+ *    except those that rewrite its device tables (dust_plan_prepare, and
+ *    the launch of a batch made with DUST_BATCH_REFRESH_PLANS): order
+ *    them against the plan's other calls (one stream, or events).
  */
 #ifndef DUST_H
 #define DUST_H
