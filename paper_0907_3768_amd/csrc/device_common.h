@@ -569,10 +569,12 @@ constexpr int PENDING_CAP = 256;
 //
 // For each (8-grain group, cell) the wave picks one evaluation, uniformly, by
 // comparing the group's hottest grain at the wave's longest wavelength
-// (smallest t over the wave's lanes) with three thresholds:
+// (smallest t over the wave's lanes) with three thresholds.  With y = 2^-t,
+// 1/(2^t - 1) = y / (1 - y) = y + y^2 + ..., and cutting the series after
+// y^n leaves the relative error y^n / (1 - y):
 //   t >= 150      every term is exactly 0 in FP32 (2^-150 underflows): skip;
-//   24 <= t       1/(2^t - 1) = y + O(y^2), y = 2^-t <= 2^-24: use y;
-//   12 <= t < 24  use y + y^2 (error y^3 <= 2^-36 relative);
+//   24 <= t       use y (relative error <= 2^-24);
+//   12 <= t < 24  use y + y^2 (relative error <= 2^-24 (1 + 2^-12));
 //   otherwise     the exact form rcp(2^t - 1).
 // The comparisons are on the float bit patterns of non-negative values (their
 // order is that of unsigned integers), so they run on the scalar unit.

@@ -300,7 +300,7 @@ def test_emission_forms_across_temperatures(dev, NL):
     wavelengths and 8 grains).
     Bound: t carries the rounding of u_l, 1/T and their product (<= 4 2^-24
     relative, i.e. <= ln 2 * 4 * 2^-24 * t relative in 2^-t), each form
-    <= 2^-24 of truncation, exp2 / rcp / the weights a few ulp,
+    about 2^-24 of truncation, exp2 / rcp / the weights a few ulp,
     and the FP32 sum over S grains S 2^-24; over the elements at least 1e-6
     of their row's peak t stays below about 40, so 2e-5 holds with room."""
     g = synth.make_grid(NL, 2, 40)
