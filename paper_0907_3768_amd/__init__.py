@@ -110,10 +110,9 @@ PROBE_EXP2, PROBE_RCP, PROBE_FMA, PROBE_EXP2_FMA, PROBE_TERM = 0, 1, 2, 3, 4
 def probe_alu(kind, blocks, iters, out, stream=None):
     """Launch one ALU throughput probe; `out` is a float32 device tensor of at
     least 256 * blocks elements (one value per thread)."""
-    if out.numel() < 256 * blocks or out.dtype.itemsize != 4 or not out.is_contiguous():
-        raise ValueError("out must be a contiguous float32 tensor of at least 256 * blocks elements")
-    _check(lib().dust_probe_alu(int(kind), int(blocks), int(iters), _vp(out.data_ptr()),
-                                _stream(stream)))
+    import torch
+    po = _vec(out, 256 * max(int(blocks), 0), "out", torch.float32)
+    _check(lib().dust_probe_alu(int(kind), int(blocks), int(iters), po, _stream(stream)))
 
 
 def last_error() -> str:
@@ -138,14 +137,47 @@ def _ptr(t):
     return _vp(t.data_ptr()) if t is not None else _vp(0)
 
 
-def _rows(t, width, name):
-    """(pointer, leading dimension) of a 2-D float32 CUDA tensor with unit column stride."""
+def _on_device(t, name, device):
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the plan on cuda:{device}")
+
+
+def _rows(t, width, name, rows=None, device=None):
+    """(pointer, leading dimension) of a 2-D float32 CUDA tensor with unit column
+    stride, at least `width` columns and at least `rows` rows: the kernels
+    touch rows 0 .. rows - 1 of it, so a shorter tensor is refused here."""
     import torch
     if t.dtype != torch.float32 or not t.is_cuda:
         raise TypeError(f"{name} must be a float32 CUDA tensor")
     if t.dim() != 2 or t.stride(1) != 1 or t.shape[1] < width:
         raise ValueError(f"{name} must be 2-D, row-major, with at least {width} columns")
+    if rows is not None and t.shape[0] < rows:
+        raise ValueError(f"{name} has {t.shape[0]} rows, the call needs {rows}")
+    _on_device(t, name, device)
     return _vp(t.data_ptr()), t.stride(0) if t.shape[0] > 1 else max(t.shape[1], width)
+
+
+def _vec(t, n, name, dtype, device=None):
+    """Pointer of a contiguous CUDA tensor of `dtype` with at least n elements,
+    or NULL for None."""
+    if t is None:
+        return _vp(0)
+    if t.dtype != dtype or not t.is_cuda:
+        raise TypeError(f"{name} must be a {dtype} CUDA tensor")
+    if not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{name} must be contiguous with at least {n} elements")
+    _on_device(t, name, device)
+    return _vp(t.data_ptr())
+
+
+def _masses(m_dust, n, device=None):
+    import torch
+    return _vec(m_dust, n, "m_dust", torch.float32, device)
+
+
+def _counters(counters, device=None):
+    import torch
+    return _vec(counters, N_COUNTERS, "counters", torch.int64, device)
 
 
 def new_counters(device="cuda"):
@@ -155,13 +187,13 @@ def new_counters(device="cuda"):
     return torch.zeros(N_COUNTERS, dtype=torch.int64, device=device)
 
 
-def _ext(Q, warm_start, width):
+def _ext(Q, warm_start, width, rows, device=None):
     """A dust_solve_ext for (Q, warm_start), or None when neither is given."""
     if Q is None and not warm_start:
         return None
     if Q is None:
         return SolveExt(None, 0, 1, 0)
-    pq, ldq = _rows(Q, width, "Q")
+    pq, ldq = _rows(Q, width, "Q", rows, device)
     return SolveExt(pq, ldq, 1 if warm_start else 0, 0)
 
 
@@ -183,6 +215,8 @@ class Plan:
         h = _vp()
         _check(lib().dust_plan_create(ctypes.byref(desc), ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
+        import torch
+        self.device = torch.cuda.current_device()  # the plan's tables live there
 
     @property
     def handle(self):
@@ -209,8 +243,8 @@ class Plan:
     def absorb(self, J, H=None, stream=None):
         n = J.shape[0]
         H = self._alloc(n, self.n_grains, J) if H is None else H
-        pj, ldj = _rows(J, self.n_lambda, "J")
-        ph, ldh = _rows(H, self.n_grains, "H")
+        pj, ldj = _rows(J, self.n_lambda, "J", n, self.device)
+        ph, ldh = _rows(H, self.n_grains, "H", n, self.device)
         _check(lib().dust_absorb(self._h, n, pj, ldj, ph, ldh, _stream(stream)))
         return H
 
@@ -221,23 +255,24 @@ class Plan:
         if warm_start and T is None:
             raise ValueError("warm_start needs T holding the previous temperatures")
         T = self._alloc(n, self.n_grains, H) if T is None else T
-        ph, ldh = _rows(H, self.n_grains, "H")
-        pt, ldt = _rows(T, self.n_grains, "T")
-        x = _ext(Q, warm_start, self.n_grains)
+        ph, ldh = _rows(H, self.n_grains, "H", n, self.device)
+        pt, ldt = _rows(T, self.n_grains, "T", n, self.device)
+        x = _ext(Q, warm_start, self.n_grains, n, self.device)
+        pc = _counters(counters, self.device)
         if x is None:
-            _check(lib().dust_solve_T(self._h, n, ph, ldh, pt, ldt, _ptr(counters),
-                                      _stream(stream)))
+            _check(lib().dust_solve_T(self._h, n, ph, ldh, pt, ldt, pc, _stream(stream)))
         else:
-            _check(lib().dust_solve_T_ext(self._h, n, ph, ldh, ctypes.byref(x), pt, ldt,
-                                          _ptr(counters), _stream(stream)))
+            _check(lib().dust_solve_T_ext(self._h, n, ph, ldh, ctypes.byref(x), pt, ldt, pc,
+                                          _stream(stream)))
         return T
 
     def emit(self, T, m_dust=None, L=None, stream=None):
         n = T.shape[0]
         L = self._alloc(n, self.n_lambda, T) if L is None else L
-        pt, ldt = _rows(T, self.n_grains, "T")
-        pl, ldl = _rows(L, self.n_lambda, "L")
-        _check(lib().dust_emit_sed(self._h, n, pt, ldt, _ptr(m_dust), pl, ldl, _stream(stream)))
+        pt, ldt = _rows(T, self.n_grains, "T", n, self.device)
+        pl, ldl = _rows(L, self.n_lambda, "L", n, self.device)
+        pm = _masses(m_dust, n, self.device)
+        _check(lib().dust_emit_sed(self._h, n, pt, ldt, pm, pl, ldl, _stream(stream)))
         return L
 
     def fused(self, J, m_dust=None, T=None, L=None, counters=None, stream=None, Q=None,
@@ -249,16 +284,18 @@ class Plan:
             raise ValueError("warm_start needs T holding the previous temperatures")
         T = self._alloc(n, self.n_grains, J) if T is None else T
         L = self._alloc(n, self.n_lambda, J) if L is None else L
-        pj, ldj = _rows(J, self.n_lambda, "J")
-        pt, ldt = _rows(T, self.n_grains, "T")
-        pl, ldl = _rows(L, self.n_lambda, "L")
-        x = _ext(Q, warm_start, self.n_grains)
+        pj, ldj = _rows(J, self.n_lambda, "J", n, self.device)
+        pt, ldt = _rows(T, self.n_grains, "T", n, self.device)
+        pl, ldl = _rows(L, self.n_lambda, "L", n, self.device)
+        pm = _masses(m_dust, n, self.device)
+        pc = _counters(counters, self.device)
+        x = _ext(Q, warm_start, self.n_grains, n, self.device)
         if x is None:
-            _check(lib().dust_run_fused(self._h, n, pj, ldj, _ptr(m_dust), pt, ldt, pl, ldl,
-                                        _ptr(counters), _stream(stream)))
+            _check(lib().dust_run_fused(self._h, n, pj, ldj, pm, pt, ldt, pl, ldl, pc,
+                                        _stream(stream)))
         else:
-            _check(lib().dust_run_fused_ext(self._h, n, pj, ldj, _ptr(m_dust), ctypes.byref(x),
-                                            pt, ldt, pl, ldl, _ptr(counters), _stream(stream)))
+            _check(lib().dust_run_fused_ext(self._h, n, pj, ldj, pm, ctypes.byref(x),
+                                            pt, ldt, pl, ldl, pc, _stream(stream)))
         return T, L
 
     def run(self, J, m_dust=None, counters=None, stream=None, Q=None, T=None,
@@ -283,10 +320,12 @@ class Batch:
         nc = arr(_i64, [j.shape[0] for j in J])
         pj, ldj, pt, ldt, pl, ldl = [], [], [], [], [], []
         for p, j, t, l in zip(plans, J, T, L):
-            a, b = _rows(j, p.n_lambda, "J"); pj.append(a.value or 0); ldj.append(b)
-            a, b = _rows(t, p.n_grains, "T"); pt.append(a.value or 0); ldt.append(b)
-            a, b = _rows(l, p.n_lambda, "L"); pl.append(a.value or 0); ldl.append(b)
-        pm = [m.data_ptr() if m is not None else 0 for m in m_dust]
+            rows = j.shape[0]
+            a, b = _rows(j, p.n_lambda, "J", rows, p.device); pj.append(a.value or 0); ldj.append(b)
+            a, b = _rows(t, p.n_grains, "T", rows, p.device); pt.append(a.value or 0); ldt.append(b)
+            a, b = _rows(l, p.n_lambda, "L", rows, p.device); pl.append(a.value or 0); ldl.append(b)
+        pm = [_masses(m, j.shape[0], p.device).value or 0 for p, m, j in zip(plans, m_dust, J)]
+        pc = _counters(counters, plans[0].device if plans else None)
         self._arrays = (hp, nc, arr(_vp, pj), arr(_i64, ldj), arr(_vp, pm), arr(_vp, pt),
                         arr(_i64, ldt), arr(_vp, pl), arr(_i64, ldl))
         h = _vp()
@@ -295,7 +334,7 @@ class Batch:
                                        ctypes.cast(a[2], _vp), ctypes.cast(a[3], _vp),
                                        ctypes.cast(a[4], _vp), ctypes.cast(a[5], _vp),
                                        ctypes.cast(a[6], _vp), ctypes.cast(a[7], _vp),
-                                       ctypes.cast(a[8], _vp), _ptr(counters),
+                                       ctypes.cast(a[8], _vp), pc,
                                        (BATCH_AUTOTUNE if autotune else 0) |
                                        (BATCH_REFRESH_PLANS if refresh_plans else 0),
                                        ctypes.byref(h)))
