@@ -421,6 +421,38 @@ def test_full_size_sampled(dev, name, mode):
 
 # --------------------------------------------------------------------------- batched persistent launch
 
+def test_batch_small_and_odd_grids(dev):
+    """A batch of grids that take the batched kernel's other paths: one grain,
+    fewer than four wavelength blocks (the tile's cells split over the
+    waves), an odd last 8-grain group, five wavelength blocks, ragged and
+    single-cell grids.  Against the oracle, and bit for bit against the
+    single-grid fused launch of each grid."""
+    shapes = [(37, 8, 1, 1), (300, 33, 3, 5), (1, 80, 2, 9), (77, 117, 2, 7),
+              (130, 250, 1, 23), (45, 150, 2, 6), (1000, 64, 1, 3)]
+    plans, Js, ms, Ts, Ls, grids, params = [], [], [], [], [], [], []
+    for k, (C, NL, ns, nz) in enumerate(shapes):
+        g = synth.make_grid(NL, ns, nz)
+        p = synth.cell_params(C, 500 + k)
+        grids.append(g)
+        params.append(p)
+        plans.append(dust.Plan(g, "mixed"))
+        Js.append(synth.radiation_field(p, g.lam, device=dev))
+        ms.append(torch.as_tensor(p.m_dust, dtype=torch.float32, device=dev))
+        Ts.append(torch.zeros((C, g.n_grains), dtype=torch.float32, device=dev))
+        Ls.append(torch.zeros((C, NL), dtype=torch.float32, device=dev))
+    say("batch of small and odd grids: create")
+    b = dust.Batch(plans, Js, ms, Ts, Ls, autotune=False, refresh_plans=True)
+    b.launch()
+    torch.cuda.synchronize()
+    for g, p, J, T, L in zip(grids, params, Js, Ts, Ls):
+        check_against_oracle(g, _host(J), p.m_dust, _host(T), _host(L))
+    for plan, J, m, T, L in zip(plans, Js, ms, Ts, Ls):
+        T1, L1 = plan.fused(J, m)
+        torch.cuda.synchronize()
+        assert torch.equal(T1, T) and torch.equal(L1, L)
+    b.close()
+
+
 @pytest.mark.parametrize("refresh", [False, True])
 def test_batch_matches_oracle_and_replays(dev, refresh):
     specs = synth.batch_specs(n_grids=12, scale=0.02)
