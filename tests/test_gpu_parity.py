@@ -419,6 +419,37 @@ def test_full_size_sampled(dev, name, mode):
     assert bool(torch.isfinite(L).all())
 
 
+# --------------------------------------------------------------------------- streams
+
+def test_calls_on_side_streams(dev):
+    """One plan used from two side streams at once (the fused form on one,
+    the three launches on the other, different inputs) gives the results of
+    the same calls on the current stream, bit for bit."""
+    g = synth.make_grid(250, 2, 40)
+    Ja, ma = _inputs(g, 3000, 21, dev)
+    Jb, mb = _inputs(g, 2000, 22, dev)
+    plan = dust.Plan(g, "mixed")
+    Ta_ref, La_ref = plan.fused(Ja, ma)
+    _, Tb_ref, Lb_ref = plan.run(Jb, mb)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+    Ta = torch.full_like(Ta_ref, -1.0)
+    La = torch.full_like(La_ref, -1.0)
+    Tb = torch.full_like(Tb_ref, -1.0)
+    Lb = torch.full_like(Lb_ref, -1.0)
+    Hb = torch.empty_like(Tb_ref)
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    for _ in range(3):
+        plan.fused(Ja, ma, Ta, La, stream=s1)
+        plan.absorb(Jb, Hb, stream=s2)
+        plan.solve(Hb, Tb, stream=s2)
+        plan.emit(Tb, mb, Lb, stream=s2)
+    torch.cuda.synchronize()
+    assert torch.equal(Ta, Ta_ref) and torch.equal(La, La_ref)
+    assert torch.equal(Tb, Tb_ref) and torch.equal(Lb, Lb_ref)
+
+
 # --------------------------------------------------------------------------- batched persistent launch
 
 def test_batch_small_and_odd_grids(dev):
