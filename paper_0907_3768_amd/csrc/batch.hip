@@ -40,6 +40,10 @@ struct GridArgs {
     int64_t ldl;
 };
 
+// J chunk width of the batched kernels: the tile's LDS is sized for the
+// batch's largest grid, so the narrower chunk keeps more workgroups resident.
+constexpr int BATCH_KC = 64;
+
 // The counter is cleared by a kernel (not a memset) so that the graph holds
 // only kernel nodes.
 __global__ void reset_counter_kernel(unsigned int* counter) {
@@ -50,7 +54,7 @@ template <int TC, int NTW>
 __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__ grids,
                                                     const int2* __restrict__ items, int n_items,
                                                     unsigned int* counter, dust_counters* cnt) {
-    extern __shared__ float sTile[];  // fused_lds_bytes(TC, Sp max)
+    extern __shared__ float sTile[];  // fused_lds_bytes(TC, Sp max, Stage<BATCH_KC>::BYTES)
     __shared__ int sItem;
     for (;;) {
         if (threadIdx.x == 0) sItem = (int)atomicAdd(counter, 1u);
@@ -63,7 +67,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__
         const int ty = __builtin_amdgcn_readfirstlane(items[it].y);
         const int2 w = make_int2(gx, ty);
         const GridArgs& g = grids[w.x];
-        fused_tile<DUST_MIXED, TC, NTW, true>(g.v, (int64_t)w.y * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L, g.ldl,
+        fused_tile<DUST_MIXED, TC, NTW, true, BATCH_KC>(g.v, (int64_t)w.y * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L, g.ldl,
                             cnt, sTile);
         // fused_tile ends with a barrier, so sItem may be overwritten now.
     }
@@ -81,13 +85,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 
                                                          const int2* __restrict__ items,
                                                          int n_items, unsigned int* counter,
                                                          dust_counters* cnt) {
-    extern __shared__ float sTile[];  // fused_lds_bytes(TC, Sp max)
+    extern __shared__ float sTile[];  // fused_lds_bytes(TC, Sp max, Stage<BATCH_KC>::BYTES)
     const int it = blockIdx.x;
     if (it >= n_items) return;
     const int gx = __builtin_amdgcn_readfirstlane(items[it].x);
     const int ty = __builtin_amdgcn_readfirstlane(items[it].y);
     const GridArgs& g = grids[gx];
-    fused_tile<DUST_MIXED, TC, NTW, true>(g.v, (int64_t)ty * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L,
+    fused_tile<DUST_MIXED, TC, NTW, true, BATCH_KC>(g.v, (int64_t)ty * TC, g.C, g.J, g.ldj, g.m, g.T, g.ldt, g.L,
                                     g.ldl, cnt, sTile);
     (void)counter;
 }
@@ -163,7 +167,7 @@ hipError_t enqueue(const dust_batch* b, const Candidate& c, hipStream_t st) {
     }
     const int blocks = persistent ? std::max(1, std::min(n_items, b->n_cu * c.per_cu))
                                   : std::max(1, n_items);
-    const size_t lds = fused_lds_bytes(c.tc, b->sp_max);
+    const size_t lds = fused_lds_bytes(c.tc, b->sp_max, Stage<BATCH_KC>::BYTES);
     hipLaunchKernelGGL(kernel_for(c.tc, c.ntw, persistent), dim3(blocks), dim3(256), lds, st,
                        (const GridArgs*)b->d_grids, items, n_items, b->d_counter, b->counters);
     return hipGetLastError();
@@ -294,7 +298,7 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
         for (int ntw : {1, 2, 4}) {
             if (ntw > 1 && ntw / 2 >= ntw_need) continue;  // no more depth than needed
             for (int per_cu : {0, 2, 4}) {
-                const size_t lds = fused_lds_bytes(tc, sp_max);
+                const size_t lds = fused_lds_bytes(tc, sp_max, Stage<BATCH_KC>::BYTES);
                 if (lds <= (size_t)max_lds && lds * std::max(per_cu, 1) <= 160u * 1024u)
                     cands.push_back(Candidate{tc, per_cu, ntw});
             }

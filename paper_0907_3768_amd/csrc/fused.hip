@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 
                                                    float* __restrict__ L, int64_t ldl,
                                                    dust_counters* cnt) {
     extern __shared__ float sTile[];
-    fused_tile<MODE, FUSED_TC, NTW, TAIL>(v, (int64_t)blockIdx.x * FUSED_TC, C, J, ldj, m, T, ldt, L,
+    fused_tile<MODE, FUSED_TC, NTW, TAIL, fused_kc(NTW)>(v, (int64_t)blockIdx.x * FUSED_TC, C, J, ldj, m, T, ldt, L,
                                           ldl, cnt, sTile);
 }
 
@@ -69,7 +69,7 @@ template <int NTW, bool TAIL>
 hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj, const float* m,
                       float* T, int64_t ldt, float* L, int64_t ldl, dust_counters* cnt,
                       hipStream_t st) {
-    const size_t lds = fused_lds_bytes(FUSED_TC, v.Sp);
+    const size_t lds = fused_lds_bytes(FUSED_TC, v.Sp, Stage<fused_kc(NTW)>::BYTES);
     const dim3 grid((unsigned)((C + FUSED_TC - 1) / FUSED_TC));
     const int km = kernel_mode(v);
     if (km == DUST_MIXED)

@@ -8,24 +8,33 @@ namespace dust {
 
 constexpr int FUSED_TC = 16;  // default cells per tile (one MFMA M-block)
 
-// LDS staging of J in chunks of 16 cells x ABS_KC wavelengths, double-
-// buffered.  Mixed mode keeps a chunk as bf16 hi and lo planes (rows padded
-// to ABS_KC + 8 values), plain mode as FP32 (rows padded to ABS_KC + 4).  The
-// padding makes a row 4 banks apart from the next, so the 16 lanes of each
-// 128-bit read phase touch every bank exactly twice.
-constexpr int ABS_KC = 128;                 // wavelengths per staged chunk
-constexpr int ABS_KSTEPS = ABS_KC / 32;     // MFMA k-steps per chunk
-constexpr int STAGE_ROW_BF16 = ABS_KC + 8;
-constexpr int STAGE_ROW_F32 = ABS_KC + 4;
-constexpr int STAGE_BUF_BYTES = 2 * 16 * STAGE_ROW_BF16 * 2;  // >= 16 * STAGE_ROW_F32 * 4
-static_assert(STAGE_BUF_BYTES >= 16 * STAGE_ROW_F32 * 4, "FP32 staging must fit");
-constexpr int STAGE_BYTES = 2 * STAGE_BUF_BYTES;
+// LDS staging of J in chunks of 16 cells x KC wavelengths, double-buffered.
+// Mixed mode keeps a chunk as bf16 hi and lo planes (rows padded to KC + 8
+// values), plain mode as FP32 (rows padded to KC + 4).  The padding makes a
+// row 4 banks apart from the next, so the 16 lanes of each 128-bit read
+// phase touch every bank exactly twice.  A chunk of 64 wavelengths halves
+// the staging's LDS (one more barrier per 64 wavelengths); that pays where
+// LDS, not registers, limits the resident workgroups (many grains).  The
+// chunk width only changes when J is staged, not the order of the MFMA
+// k-steps, so the heating is the same bit for bit.
+template <int KC>
+struct Stage {
+    static_assert(KC % 32 == 0 && (KC / 16) % 2 == 0, "chunk of whole k-steps");
+    static constexpr int KSTEPS = KC / 32;     // MFMA k-steps per chunk
+    static constexpr int ROW_BF16 = KC + 8;
+    static constexpr int ROW_F32 = KC + 4;
+    static constexpr int BUF_BYTES = 2 * 16 * ROW_BF16 * 2;  // >= 16 * ROW_F32 * 4
+    static_assert(BUF_BYTES >= 16 * ROW_F32 * 4, "FP32 staging must fit");
+    static constexpr int BYTES = 2 * BUF_BYTES;
+};
+constexpr int ABS_KC = 128;  // default chunk width
+constexpr int STAGE_BYTES = Stage<ABS_KC>::BYTES;
 
 // Phase 1: heating of a 16-cell block into sH[16][Sp] (rows of the tile's
 // LDS array) in the plan's scaled units H' = H 2^es, on the MFMA units.
 //
-// J streams through LDS in chunks of ABS_KC wavelengths: every thread loads
-// ABS_KC/16 values of the next chunk (thread t: row t/16, column pairs
+// J streams through LDS in chunks of KC wavelengths: every thread loads
+// KC/16 values of the next chunk (thread t: row t/16, column pairs
 // 2 (t mod 16) + 32 i) while the current chunk is multiplied, then splits
 // them (mixed: bf16 hi + lo) into the other buffer; one barrier per chunk.
 // Each wave multiplies with its grain tiles w, w+4, ... (NTW of them per
@@ -37,7 +46,7 @@ constexpr int STAGE_BYTES = 2 * STAGE_BUF_BYTES;
 // 16x16x4 FP32 MFMAs in which MFMA i takes k0 + 8q + i.  Any assignment of
 // wavelengths to MFMA k-slots gives the same sum as long as both operands
 // use it.
-template <int MODE, int NTW>
+template <int MODE, int NTW, int KC = ABS_KC>
 __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int64_t C,
                                              const float* __restrict__ J, int64_t ldj,
                                              float* sH, char* sStage) {
@@ -47,9 +56,9 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
     const int wave = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int tiles = v.Sp / 16;
-    // loader role: 256 threads x ABS_KC/16 values = one 16 x ABS_KC chunk
-    constexpr int NX = ABS_KC / 16;  // values per thread
-    static_assert(ABS_KC % 32 == 0 && NX % 2 == 0, "chunk of whole k-steps");
+    // loader role: 256 threads x KC/16 values = one 16 x KC chunk
+    using St = Stage<KC>;
+    constexpr int NX = KC / 16;  // values per thread
     const int lrow = tid >> 4, lcol = (tid & 15) * 2;
     const bool lrow_ok = c0 + lrow < C;
     const float* jl = J + (lrow_ok ? c0 + lrow : 0) * ldj;
@@ -64,21 +73,21 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
     };
     // this thread's first slot in a staging buffer; the other slots are
     // constant offsets from it (lcol is even)
-    const int slot0 = BF ? (lrow * STAGE_ROW_BF16 + lcol) / 2 : (lrow * STAGE_ROW_F32 + lcol) / 2;
+    const int slot0 = BF ? (lrow * St::ROW_BF16 + lcol) / 2 : (lrow * St::ROW_F32 + lcol) / 2;
     auto store_j = [&](int buf, const float (&x)[NX]) {
-        char* base = sStage + buf * STAGE_BUF_BYTES;
+        char* base = sStage + buf * St::BUF_BYTES;
 #pragma unroll
         for (int i = 0; i < NX / 2; ++i) {
             const float x0 = x[2 * i], x1 = x[2 * i + 1];
             if constexpr (BF) {
-                // [hi|lo][16 rows][STAGE_ROW_BF16] bf16; a pair of columns per 32-bit store
+                // [hi|lo][16 rows][ROW_BF16] bf16; a pair of columns per 32-bit store
                 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
                 const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
                 const bf16x2 hi = {h0, h1};
                 const bf16x2 lo = {(__bf16)(x0 - (float)h0), (__bf16)(x1 - (float)h1)};
                 bf16x2* b = reinterpret_cast<bf16x2*>(base) + slot0;
                 b[16 * i] = hi;
-                b[8 * STAGE_ROW_BF16 + 16 * i] = lo;
+                b[8 * St::ROW_BF16 + 16 * i] = lo;
             } else {
                 float2* b = reinterpret_cast<float2*>(base) + slot0;
                 b[16 * i] = make_float2(x0, x1);
@@ -113,7 +122,7 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
         }
     };
 
-    const int nchunks = (nsteps + ABS_KSTEPS - 1) / ABS_KSTEPS;
+    const int nchunks = (nsteps + St::KSTEPS - 1) / St::KSTEPS;
     // Grain tiles in groups of 4 NTW (one pass over J each).
     for (int tg = 0; tg < tiles; tg += 4 * NTW) {
         f32x4 acc[NTW];
@@ -125,19 +134,19 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
         __syncthreads();
         for (int ch = 0; ch < nchunks; ++ch) {
             const int buf = ch & 1;
-            if (ch + 1 < nchunks) load_j((ch + 1) * ABS_KC, x);  // next chunk in flight
+            if (ch + 1 < nchunks) load_j((ch + 1) * KC, x);  // next chunk in flight
 #pragma unroll 1
-            for (int ks = 0; ks < ABS_KSTEPS; ++ks) {
-                const int step = ch * ABS_KSTEPS + ks;
+            for (int ks = 0; ks < St::KSTEPS; ++ks) {
+                const int step = ch * St::KSTEPS + ks;
                 if (step >= nsteps) break;  // uniform
                 KFrag kc;
                 load_k(tg, step * 32, kc);
                 if constexpr (BF) {
-                    const __bf16* b = reinterpret_cast<const __bf16*>(sStage + buf * STAGE_BUF_BYTES);
+                    const __bf16* b = reinterpret_cast<const __bf16*>(sStage + buf * St::BUF_BYTES);
                     const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(
-                        b + row * STAGE_ROW_BF16 + ks * 32 + kq * 8);
+                        b + row * St::ROW_BF16 + ks * 32 + kq * 8);
                     const bf16x8 alo = *reinterpret_cast<const bf16x8*>(
-                        b + 16 * STAGE_ROW_BF16 + row * STAGE_ROW_BF16 + ks * 32 + kq * 8);
+                        b + 16 * St::ROW_BF16 + row * St::ROW_BF16 + ks * 32 + kq * 8);
 #pragma unroll
                     for (int t = 0; t < NTW; ++t) {
                         if (tg + wave + 4 * t < tiles) {
@@ -147,11 +156,11 @@ __device__ __forceinline__ void fused_absorb(const PlanView& v, int64_t c0, int6
                         }
                     }
                 } else {
-                    const float* b = reinterpret_cast<const float*>(sStage + buf * STAGE_BUF_BYTES);
+                    const float* b = reinterpret_cast<const float*>(sStage + buf * St::BUF_BYTES);
                     const float4 a0 = *reinterpret_cast<const float4*>(
-                        b + row * STAGE_ROW_F32 + ks * 32 + kq * 8);
+                        b + row * St::ROW_F32 + ks * 32 + kq * 8);
                     const float4 a1 = *reinterpret_cast<const float4*>(
-                        b + row * STAGE_ROW_F32 + ks * 32 + kq * 8 + 4);
+                        b + row * St::ROW_F32 + ks * 32 + kq * 8 + 4);
                     const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
                     for (int t = 0; t < NTW; ++t) {
@@ -288,7 +297,7 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
     const int n = TC * v.Sp;
     fused_solve<MODE, TC>(v, c0, C, T, ldt, cnt, sH,
                           reinterpret_cast<int*>(reinterpret_cast<char*>(sH) +
-                                                 emit_lds_bytes(TC, v.Sp) + STAGE_BYTES));
+                                                 emit_lds_bytes(TC, v.Sp)));
     __syncthreads();
     uint32_t* sChunk = reinterpret_cast<uint32_t*>(sH + n);
     fill_chunk_min<TC>(sH, sChunk, v.Sp);
@@ -308,27 +317,40 @@ __device__ __forceinline__ void fused_solve_emit(const PlanView& v, int64_t c0, 
     }
 }
 
-// LDS bytes of a fused tile of TC cells: the emission tile (whose first
-// TC x Sp floats hold H' and then 1/T), the J staging buffers and the solve
-// phase's pending list.
-__host__ __device__ constexpr size_t fused_lds_bytes(int TC, int Sp) {
-    return emit_lds_bytes(TC, Sp) + STAGE_BYTES + SOLVE_LDS_BYTES;
+// LDS bytes of a fused tile of TC cells.  The first TC x Sp floats hold H'
+// and then 1/T throughout.  Behind them the J staging buffers of the heating
+// share the space with what only the later phases use: the emission's group
+// minima (sChunk, sPair) and the solve's pending list, which follows them.
+// The heating's last read of the staging precedes a barrier, so the sharing
+// needs no extra synchronisation; it lowers the LDS a workgroup holds, and
+// with it the limit on resident workgroups, by the smaller of the two.
+__host__ __device__ constexpr size_t fused_lds_bytes(int TC, int Sp, int stage_bytes) {
+    return (size_t)TC * Sp * sizeof(float) + stage_bytes >
+                   emit_lds_bytes(TC, Sp) + SOLVE_LDS_BYTES
+               ? (size_t)TC * Sp * sizeof(float) + stage_bytes
+               : emit_lds_bytes(TC, Sp) + SOLVE_LDS_BYTES;
 }
 
-// One tile of TC cells (TC a multiple of 16) starting at cell c0; lds holds
-// fused_lds_bytes(TC, Sp) bytes.  Ends with every thread past its last read
-// of the tile's LDS.
-template <int MODE, int TC, int NTW, bool TAIL>
+// Chunk width of the single-grid fused kernel: with three or four grain
+// tiles per wave (more than 128 grains) the tile's LDS, not its registers,
+// limits the resident workgroups, and the narrower chunk lifts that limit.
+__host__ __device__ constexpr int fused_kc(int ntw) { return ntw >= 3 ? 64 : 128; }
+
+// One tile of TC cells (TC a multiple of 16) starting at cell c0, J staged in
+// chunks of KC wavelengths; lds holds fused_lds_bytes(TC, Sp,
+// Stage<KC>::BYTES) bytes.  Ends with every thread past its last read of the
+// tile's LDS.
+template <int MODE, int TC, int NTW, bool TAIL, int KC>
 __device__ __forceinline__ void fused_tile(const PlanView& v, int64_t c0, int64_t C,
                                            const float* __restrict__ J, int64_t ldj,
                                            const float* __restrict__ m, float* __restrict__ T,
                                            int64_t ldt, float* __restrict__ L, int64_t ldl,
                                            dust_counters* cnt, float* lds) {
     float* sH = lds;
-    char* sStage = reinterpret_cast<char*>(lds) + emit_lds_bytes(TC, v.Sp);
+    char* sStage = reinterpret_cast<char*>(lds + TC * v.Sp);  // shared, see fused_lds_bytes
 #pragma unroll
     for (int mb = 0; mb < TC / 16; ++mb)
-        fused_absorb<MODE, NTW>(v, c0 + 16 * mb, C, J, ldj, sH + 16 * mb * v.Sp, sStage);
+        fused_absorb<MODE, NTW, KC>(v, c0 + 16 * mb, C, J, ldj, sH + 16 * mb * v.Sp, sStage);
     __syncthreads();
     fused_solve_emit<MODE, TC, TAIL>(v, c0, C, m, T, ldt, L, ldl, cnt, sH);
     __syncthreads();
