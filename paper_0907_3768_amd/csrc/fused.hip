@@ -7,16 +7,17 @@
 namespace dust {
 namespace {
 
-// Resident waves per SIMD: six (80 VGPRs) for grids of up to 128 grains --
-// more tiles in flight keep the phases of different tiles overlapping; the
-// compiler spills only inside the exact fallback for out-of-table pairs,
-// which tiles without such pairs branch over; measured 4 % faster than
-// five, seven slower.  Five (96 VGPRs) for more grains, whose heating
-// accumulators would spill at six.
+// Resident waves per SIMD: six (80 VGPRs) -- more tiles in flight keep the
+// phases of different tiles overlapping.  Up to 128 grains the compiler
+// spills only inside the exact fallback for out-of-table pairs, which tiles
+// without such pairs branch over; measured 4 % faster than five, seven
+// slower.  Above 128 grains (three or four grain tiles per wave, J in
+// 64-wavelength chunks) a few heating values spill too, and six waves still
+// measured 0.4-2.6 % faster than five.
 // TAIL: the emission's odd last grain group is its own step (grids whose
 // grain count leaves an odd number of 8-grain groups).
 template <int MODE, int NTW, bool TAIL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 6 : 5, 8))) void fused_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void fused_kernel(
     PlanView v, int64_t C,
                                                    const float* __restrict__ J, int64_t ldj,
                                                    const float* __restrict__ m,
