@@ -452,12 +452,15 @@ def test_calls_on_side_streams(dev):
 
 # --------------------------------------------------------------------------- batched persistent launch
 
-def test_batch_small_and_odd_grids(dev):
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batch_small_and_odd_grids(dev, autotune):
     """A batch of grids that take the batched kernel's other paths: one grain,
     fewer than four wavelength blocks (the tile's cells split over the
     waves), an odd last 8-grain group, five wavelength blocks, ragged and
     single-cell grids.  Against the oracle, and bit for bit against the
-    single-grid fused launch of each grid."""
+    single-grid fused launch of each grid.  With autotune every candidate
+    (16- and 32-cell tiles, one workgroup per item or a work queue) runs on
+    these grids while the batch is made, and the chosen one is checked."""
     shapes = [(37, 8, 1, 1), (300, 33, 3, 5), (1, 80, 2, 9), (77, 117, 2, 7),
               (130, 250, 1, 23), (45, 150, 2, 6), (1000, 64, 1, 3)]
     plans, Js, ms, Ts, Ls, grids, params = [], [], [], [], [], [], []
@@ -471,8 +474,9 @@ def test_batch_small_and_odd_grids(dev):
         ms.append(torch.as_tensor(p.m_dust, dtype=torch.float32, device=dev))
         Ts.append(torch.zeros((C, g.n_grains), dtype=torch.float32, device=dev))
         Ls.append(torch.zeros((C, NL), dtype=torch.float32, device=dev))
-    say("batch of small and odd grids: create")
-    b = dust.Batch(plans, Js, ms, Ts, Ls, autotune=False, refresh_plans=True)
+    say(f"batch of small and odd grids: create (autotune={autotune})")
+    b = dust.Batch(plans, Js, ms, Ts, Ls, autotune=autotune, refresh_plans=True)
+    say("batch info", b.info())
     b.launch()
     torch.cuda.synchronize()
     for g, p, J, T, L in zip(grids, params, Js, Ts, Ls):
