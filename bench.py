@@ -31,6 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "(cell,grain) temperatures/s incl. SED; mixed vs plain FP32 at rel T err ≤1e-4"
+# 4194304 cells x 1000 wavelengths x 3 species x 80 sizes: the largest workload
+# that fits one GPU (16.8 GB of J), mixed precision, fused absorb -> solve -> emit.
+DEFAULT_WORKLOAD = "full-4194304x1000x240"
+# Strided cells of the oracle's CPU baseline on the million-cell workloads.
+CPU_SAMPLE_CELLS = 4096
 UNIT = "(cell,grain) temperatures/s"
 
 # MI355X (gfx950) unit counts and clock.
@@ -76,6 +81,42 @@ def measured_traffic(kernel_key, src_hash):
     if not e or e.get("source_hash") != src_hash:
         return None
     return e.get("bytes_per_launch")
+
+
+def committed_json(name):
+    try:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
+def issue_figures(kernel_key, src_hash, kernel_ms, terms):
+    """Utilisation of the dominant kernel's vector issue: its VALU and
+    transcendental wave instructions (committed rocprofv3 --pmc counts, taken
+    on the same sources) priced at the ALU probe's measured cycles per SIMD,
+    over what 1024 SIMDs at 2.4 GHz offer in the measured duration.  Also the
+    rate of exact Planck terms the probe's cost of one such term allows."""
+    probe = committed_json("alu_probe.json")
+    out = {}
+    if probe:
+        cyc = {k: v["cycles_per_wave_step_at_2.4GHz"] for k, v in probe["alu_probe"].items()}
+        # one wave instruction of the exact term covers 64 terms
+        out["exact_term_peak"] = N_CU * SIMD_PER_CU * CLOCK_HZ * 64 / cyc["term"] / 1e9
+        out["frac_of_exact_term_peak"] = terms / (kernel_ms * 1e-3) / 1e9 / out["exact_term_peak"]
+    counts = committed_json("counters.json")
+    e = (counts or {}).get(kernel_key)
+    if probe and e and e.get("source_hash") == src_hash:
+        trans = e["SQ_INSTS_VALU_TRANS_F32"]
+        other = e["SQ_INSTS_VALU"] - trans
+        busy = trans * cyc["exp2"] + other * cyc["fma"]
+        out["issue_frac"] = busy / (N_CU * SIMD_PER_CU * CLOCK_HZ * kernel_ms * 1e-3)
+        out["issue_model"] = ("(TRANS x %.2f + other VALU x %.2f cycles) / (1024 SIMDs x 2.4 GHz x "
+                              "duration); counts from profiles/counters.json, cycles from "
+                              "profiles/alu_probe.json" % (cyc["exp2"], cyc["fma"]))
+    else:
+        out["issue_frac"] = None
+    return out
 
 
 class Timer:
@@ -151,8 +192,9 @@ def check_sample(grid, J, m_host, T, L, n_sample=64, table=None):
             "SED_weighted_ratio_dev": se["weighted_ratio_dev"]}
 
 
-def cpu_baseline(grid, J, m_host, target_s):
-    """The oracle as it stands, on the host cores, on a strided sample of cells."""
+def cpu_baseline(grid, J, m_host, target_s, n_cells=None):
+    """The oracle as it stands, on the host cores, on a strided sample of
+    cells: `n_cells` of them, or as many as take about `target_s` seconds."""
     import oracle
     import torch
     C = J.shape[0]
@@ -165,11 +207,15 @@ def cpu_baseline(grid, J, m_host, target_s):
         oracle.run(grid, Jh, m_host[rows])
         return time.perf_counter() - t0
 
-    n = min(256, C)
-    dt = run(n)
-    n2 = int(min(C, max(n, n * target_s / max(dt, 1e-3))))
-    if n2 > n:
-        n, dt = n2, run(n2)
+    if n_cells is not None:
+        n = min(C, n_cells)
+        dt = run(n)
+    else:
+        n = min(256, C)
+        dt = run(n)
+        n2 = int(min(C, max(n, n * target_s / max(dt, 1e-3))))
+        if n2 > n:
+            n, dt = n2, run(n2)
     return {"value": n * S / dt, "unit": UNIT, "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{n} strided cells of the workload ({n * S} pairs, FP64 oracle incl. SED), "
                       f"{dt:.1f} s"}
@@ -303,6 +349,22 @@ def run_batch(args, torch, synth, dust, dev):
     mixed_ms, mixed_k = time_steps(torch, [("graph", lambda: batch.launch())], args.steps, args.warmup)
     kern_ms, kern_k = time_steps(torch, [("batch_kernel", lambda: batch_k.launch())], args.steps,
                                  args.warmup)
+    # every launch form the autotuner chooses from, pinned one at a time
+    log("timing every batched launch form")
+    forms_ms = {}
+    for tc in (16, 32):
+        for ntw in (1, 2, 4):
+            for per_cu in (0, 2, 4, 6):
+                os.environ["DUST_BATCH_CANDIDATE"] = f"{tc},{ntw},{per_cu}"
+                try:
+                    bf = dust.Batch(plans, Js, ms, Ts, Ls, counters=cnt, autotune=False)
+                except dust.DustError:
+                    continue  # does not fit this batch
+                finally:
+                    del os.environ["DUST_BATCH_CANDIDATE"]
+                f_ms, _ = time_steps(torch, [("form", lambda: bf.launch())], 3, 1)
+                forms_ms[f"tc={tc},ntw={ntw},per_cu={per_cu}"] = f_ms
+                bf.close()
     cnt.zero_()
     batch.launch()
     torch.cuda.synchronize()
@@ -355,6 +417,8 @@ def run_batch(args, torch, synth, dust, dev):
                      "source_hash": src},
         "sed_cells_per_s": cells / (mixed_ms * 1e-3),
         "stages_ms": {"graph": mixed_k["graph"], "batch_kernel_only": kern_k["batch_kernel"]},
+        "launch_forms_ms": forms_ms,
+        "chosen_form": dict(zip(("cells_per_tile", "tiles_per_wave", "per_cu"), batch.form())),
         "errors": mixed_err,
         "counters": dict(zip(COUNTER_NAMES, mixed_cnt)),
         "plain_fp32": {"value": plain_value, "ms_per_step": plain_ms, "errors": plain_err,
@@ -387,21 +451,51 @@ def run_batch(args, torch, synth, dust, dev):
     return 0 if ok else 3
 
 
+PROBE_KINDS = (("exp2", 0), ("rcp", 1), ("fma", 2), ("exp2+fma", 3), ("term", 4))
+
+
+def probe_lib():
+    """The measurement-only ALU probe library (libdust_probe.so)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_0907_3768_amd", "libdust_probe.so")
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_0907_3768_amd.build()")
+    L = ctypes.CDLL(path)
+    L.alu_probe_run.restype = ctypes.c_int
+    L.alu_probe_run.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                ctypes.c_void_p]
+    return L
+
+
+def probe_launch(L, kind, blocks, iters, out):
+    """One probe launch on the current stream; `out` a float32 CUDA tensor of
+    at least 256 * blocks elements."""
+    import ctypes
+    import torch
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float32 CUDA tensor")
+    if out.numel() < 256 * blocks:
+        raise ValueError(f"out needs {256 * blocks} elements")
+    rc = L.alu_probe_run(int(kind), int(blocks), int(iters), ctypes.c_void_p(out.data_ptr()),
+                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"alu_probe_run failed ({rc})")
+
+
 def run_alu_probe():
     """Rates of the vector ALU forms the kernels are built from, per second and
     per SIMD cycle at the 2.4 GHz peak clock (256 CUs x 4 SIMDs)."""
     import torch
-    import paper_0907_3768_amd as dust
+    L = probe_lib()
     blocks, iters, chains = 256 * 16, 4096, 8
     out = torch.empty(256 * blocks, dtype=torch.float32, device="cuda:0")
     res = {}
-    for name, kind in (("exp2", dust.PROBE_EXP2), ("rcp", dust.PROBE_RCP), ("fma", dust.PROBE_FMA),
-                       ("exp2+fma", dust.PROBE_EXP2_FMA), ("term", dust.PROBE_TERM)):
-        dust.probe_alu(kind, blocks, iters, out)  # warm-up
-        settle(torch, [("probe", lambda: dust.probe_alu(kind, blocks, 64, out))], 0.1)
+    for name, kind in PROBE_KINDS:
+        probe_launch(L, kind, blocks, iters, out)  # warm-up
+        settle(torch, [("probe", lambda: probe_launch(L, kind, blocks, 64, out))], 0.1)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        dust.probe_alu(kind, blocks, iters, out)
+        probe_launch(L, kind, blocks, iters, out)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -419,11 +513,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain-262144x250x80",
-                    help="plain-262144x250x80 (default), small-1024x120x20, "
-                         "mixed-1048576x500x128, full-4194304x1000x240 or batch-64grids")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
+                    help="full-4194304x1000x240 (default: the largest single-GPU workload), "
+                         "small-1024x120x20, plain-262144x250x80, mixed-1048576x500x128 or "
+                         "batch-64grids")
+    ap.add_argument("--secondary-steps", type=int, default=5,
+                    help="timed steps of each secondary form (at most --steps; one warm-up)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target CPU time of the oracle baseline sample")
+                    help="target CPU time of the oracle baseline sample (workloads below a "
+                         "million cells; the larger ones time a fixed 4096-cell sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--alu-probe", action="store_true",
                     help="only run the ALU throughput probes (v_exp_f32, v_rcp_f32, v_fma_f32, "
@@ -530,6 +628,9 @@ def main():
             "hbm_GBps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9,
             "hbm_frac_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "source_hash": src}
+    # Beside the term-equivalent fraction (which the cheap emission forms can
+    # push past 1): the vector issue utilisation and the exact-term ceiling.
+    roof.update(issue_figures("fused_mixed:" + w.name, src, fused_ms, terms))
 
     out = {
         "metric": METRIC,
@@ -565,11 +666,14 @@ def main():
         print(json.dumps(out), flush=True)
         return 0 if mixed_ok else 3
 
+    # secondary forms: fewer steps, so that the default run stays within minutes
+    k2, w2 = max(1, min(args.steps, args.secondary_steps)), min(args.warmup, 1)
+
     log("timing mixed path with the FP32 inverse-table lookup")
     pf = dust.Plan(grid, "mixed", f32_lookup=True)
     f32_stages = [("prepare", lambda: pf.prepare()),
                   ("fused", lambda: pf.fused(J, m, T, L, counters=cnt))]
-    f32_ms, f32_k = time_steps(torch, f32_stages, args.steps, args.warmup)
+    f32_ms, f32_k = time_steps(torch, f32_stages, k2, w2)
     f32_err = check_sample(grid, J, params.m_dust, T, L)
     del pf
 
@@ -577,17 +681,17 @@ def main():
     pm2 = dust.Plan(grid, "mixed", fused_kernels=2)
     f2_stages = [("prepare", lambda: pm2.prepare()),
                  ("fused2", lambda: pm2.fused(J, m, T, L, counters=cnt))]
-    f2_ms, f2_k = time_steps(torch, f2_stages, args.steps, args.warmup)
+    f2_ms, f2_k = time_steps(torch, f2_stages, k2, w2)
 
     log("timing mixed path as three launches")
     sep_stages = [("prepare", lambda: pm.prepare()),
                   ("absorb", lambda: pm.absorb(J, H)),
                   ("solve", lambda: pm.solve(H, T, counters=cnt)),
                   ("emit", lambda: pm.emit(T, m, L))]
-    sep_ms, sep_k = time_steps(torch, sep_stages, args.steps, args.warmup)
+    sep_ms, sep_k = time_steps(torch, sep_stages, k2, w2)
 
     log("timing plain FP32 path")
-    plain_ms, plain_k = time_steps(torch, plain_stages, args.steps, args.warmup)
+    plain_ms, plain_k = time_steps(torch, plain_stages, k2, w2)
     cnt.zero_()
     pp.run(J, m, counters=cnt)
     torch.cuda.synchronize()
@@ -598,28 +702,32 @@ def main():
     Q = torch.as_tensor(synth.extra_heating(grid, C, 78), device=dev)
     q_stages = [("prepare", lambda: pm.prepare()),
                 ("fused", lambda: pm.fused(J, m, T, L, counters=cnt, Q=Q))]
-    q_ms, q_k = time_steps(torch, q_stages, args.steps, args.warmup)
+    q_ms, q_k = time_steps(torch, q_stages, k2, w2)
     del Q
 
     # The step with J coming from, and T and L going back to, pinned host
     # memory (what the paper's "GPU" timing included): context, never `value`.
+    # On at most 2^20 cells (the transfers scale with the cells; pinning the
+    # 4M-cell workload's 38 GB of host buffers would take longer than the rest).
     log("timing the mixed step with host transfers")
-    J_host = torch.empty((C, NL), dtype=torch.float32, pin_memory=True)
-    T_host = torch.empty((C, S), dtype=torch.float32, pin_memory=True)
-    L_host = torch.empty((C, NL), dtype=torch.float32, pin_memory=True)
-    J_host.copy_(J)
-    J_dev = torch.empty_like(J)
+    Cx = min(C, 1 << 20)
+    J_host = torch.empty((Cx, NL), dtype=torch.float32, pin_memory=True)
+    T_host = torch.empty((Cx, S), dtype=torch.float32, pin_memory=True)
+    L_host = torch.empty((Cx, NL), dtype=torch.float32, pin_memory=True)
+    J_host.copy_(J[:Cx])
+    J_dev = torch.empty((Cx, NL), dtype=torch.float32, device=dev)
+    Tx, Lx, mx = T[:Cx], L[:Cx], m[:Cx]
     xfer_stages = [("h2d_J", lambda: J_dev.copy_(J_host, non_blocking=True)),
                    ("prepare", lambda: pm.prepare()),
-                   ("fused", lambda: pm.fused(J_dev, m, T, L, counters=cnt)),
-                   ("d2h_T_L", lambda: (T_host.copy_(T, non_blocking=True),
-                                        L_host.copy_(L, non_blocking=True)))]
-    xfer_ms, xfer_k = time_steps(torch, xfer_stages, args.steps, args.warmup)
-    xfer_bytes = 4 * (C * NL + C * S + C * NL)
+                   ("fused", lambda: pm.fused(J_dev, mx, Tx, Lx, counters=cnt)),
+                   ("d2h_T_L", lambda: (T_host.copy_(Tx, non_blocking=True),
+                                        L_host.copy_(Lx, non_blocking=True)))]
+    xfer_ms, xfer_k = time_steps(torch, xfer_stages, k2, w2)
+    xfer_bytes = 4 * (Cx * NL + Cx * S + Cx * NL)
     del J_host, T_host, L_host, J_dev
 
     log("timing the table-linear mode")
-    table_leg = run_table_leg(torch, dust, grid, params, J, m, T, L, cnt, args.steps, args.warmup)
+    table_leg = run_table_leg(torch, dust, grid, params, J, m, T, L, cnt, k2, w2)
 
     log("timing re-heating passes")
     reheat_leg = run_reheat_leg(torch, synth, dust, grid, params, J, m, T, L, cnt)
@@ -645,8 +753,8 @@ def main():
                 "emit": {"bound": "alu", "Gterm_per_s": terms / (sep_k["emit"] * 1e-3) / 1e9,
                          "frac": terms / (sep_k["emit"] * 1e-3) / TERM_PEAK_PER_S,
                          "hbm_frac": 4.0 * (C * S + C * NL) / (sep_k["emit"] * 1e-3) / 1e9 / HBM_PEAK_GBS}}},
-        "transfer_inclusive": {"ms_per_step": xfer_ms, "stages_ms": xfer_k,
-                               "value": pairs / (xfer_ms * 1e-3), "pcie_bytes": xfer_bytes,
+        "transfer_inclusive": {"ms_per_step": xfer_ms, "stages_ms": xfer_k, "cells": Cx,
+                               "value": Cx * S / (xfer_ms * 1e-3), "pcie_bytes": xfer_bytes,
                                "note": "J host->device and T, L device->host from pinned memory "
                                        "around the step; context for the paper's GPU column"},
         "mixed_f32_lookup": {"ms_per_step": f32_ms, "stages_ms": f32_k,
@@ -659,7 +767,8 @@ def main():
     })
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(grid, J, params.m_dust, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(grid, J, params.m_dust, args.cpu_seconds,
+                                           CPU_SAMPLE_CELLS if C >= (1 << 20) else None)
     tpar = table_leg["parity_vs_oracle_table"]
     rerr = reheat_leg["errors_last_pass_vs_oracle"]
     ok = (mixed_ok and plain_err["T_max_rel"] <= 1e-4 and plain_err["SED_max_rel"] <= 1e-3 and

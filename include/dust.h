@@ -28,7 +28,8 @@
  *    least the row width (NL for J and L, S for H and T).
  *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
  *    work: they neither allocate nor synchronise, except dust_plan_create,
- *    dust_plan_destroy, dust_batch_create and dust_batch_destroy.
+ *    dust_plan_destroy, dust_batch_create, dust_batch_destroy and
+ *    dust_batch_run (a stream-ordered allocation of its work list).
  *  - Every argument is checked before any HIP call; a bad argument returns
  *    DUST_EINVAL and the reason is available from dust_last_error().
  *  - Numerical conditions are not errors.  They are counted in an optional
@@ -210,18 +211,24 @@ dust_status dust_run_fused_ext(dust_plan* plan, int64_t n_cells,
                                float* T, int64_t ldt, float* L, int64_t ldl,
                                dust_counters* counters, void* stream);
 
-/* Many independent grids in one launch.  A batch binds plans and
- * buffers once (host arrays of length n_grids; m_dust[g] may be NULL), builds
- * the work list of (grid, cell tile) items ordered by cost and records one HIP
- * graph.  Flags:
+/* Many independent grids in one launch (the batching of Section 4's
+ * per-cell-block decomposition over several grids; each grid is its own
+ * plan).  A batch binds plans and buffers once (host arrays of length
+ * n_grids; m_dust[g] may be NULL), builds the work list of (grid, cell tile)
+ * items ordered by cost and records one HIP graph.  Flags:
  *   DUST_BATCH_AUTOTUNE       pick the launch form (one workgroup per item,
- *                             or a work queue) and the tile shape (cells per tile, resident
- *                             workgroups per CU) by timing candidate launches
- *                             on the bound buffers, which it overwrites;
+ *                             or a work queue with 2, 4 or 6 resident
+ *                             workgroups per CU), the cells per tile (16 or
+ *                             32) and the grain tiles per wave by timing
+ *                             candidate launches on the bound buffers, which
+ *                             it overwrites;
  *   DUST_BATCH_REFRESH_PLANS  the graph first re-derives every plan's tables
  *                             (dust_plan_prepare), so one replay is the whole
  *                             path for every grid.
- * All plans must be DUST_MIXED plans of the current device. */
+ * Every launch form gives the same results, bit for bit, as dust_run_fused
+ * on each grid.  All plans must be DUST_MIXED plans (FP64 lookup) of the
+ * current device.  Allocates device memory and synchronises (it runs the
+ * autotuner's candidates). */
 typedef struct dust_batch dust_batch;
 
 enum { DUST_BATCH_AUTOTUNE = 1, DUST_BATCH_REFRESH_PLANS = 2 };
@@ -242,33 +249,31 @@ dust_status dust_batch_launch(dust_batch* batch, void* stream);
 dust_status dust_batch_info(const dust_batch* batch, int32_t* cells_per_tile,
                             int64_t* n_items);
 
+/* The batch's launch form: cells per tile, grain tiles per wave in one
+ * heating pass, and resident workgroups per CU of the work-queue form (0: one
+ * workgroup per item).  Any pointer may be NULL. */
+dust_status dust_batch_form(const dust_batch* batch, int32_t* cells_per_tile,
+                            int32_t* tiles_per_wave, int32_t* per_cu);
+
 dust_status dust_batch_destroy(dust_batch* batch);
 
-/* --- Measurement ----------------------------------------------------------
-   Throughput probes of the vector ALU forms the hot path is built from, for
-   checking the ALU peak used in roofline figures on the device at hand (not
-   part of the method).  `blocks` workgroups of 256 threads each run `iters`
-   iterations of 8 independent dependency chains of the chosen form:
-     DUST_PROBE_EXP2      v_exp_f32
-     DUST_PROBE_RCP       v_rcp_f32
-     DUST_PROBE_FMA       v_fma_f32
-     DUST_PROBE_EXP2_FMA  v_exp_f32 plus an independent v_fma_f32 per step
-                          (shows whether other VALU work issues alongside the
-                          transcendental pipe)
-     DUST_PROBE_TERM      the emission's exact Planck term (mul, exp, sub,
-                          rcp, fma)
-   and writes one float per thread to the device buffer `out` (caller-owned,
-   at least 256 * blocks floats).  Returns DUST_EINVAL for blocks or iters
-   outside [1, 2^20], a NULL `out` or an unknown kind; launches only (time it
-   with events on `stream`). */
-enum {
-    DUST_PROBE_EXP2 = 0,
-    DUST_PROBE_RCP = 1,
-    DUST_PROBE_FMA = 2,
-    DUST_PROBE_EXP2_FMA = 3,
-    DUST_PROBE_TERM = 4
-};
-dust_status dust_probe_alu(int32_t kind, int32_t blocks, int32_t iters, float* out, void* stream);
+/* One-shot batched launch on `stream`: the same arguments and checks as
+ * dust_batch_create, the same results, but nothing is kept.  The work list
+ * (the grids' launch arguments and the (grid, tile) items) is built on the
+ * host, copied into a stream-ordered device allocation (hipMallocAsync,
+ * released with hipFreeAsync after the kernel on the same stream) and the
+ * batched kernel runs once, one workgroup per 16-cell item (the batch's
+ * default form; no autotuning, no plan refresh).  The host copy is from
+ * pageable memory, so the call may wait for `stream`'s earlier work before
+ * it returns; it cannot be recorded into a HIP graph (use dust_batch_create,
+ * whose graph does the same work). */
+dust_status dust_batch_run(dust_plan* const* plans, int32_t n_grids,
+                           const int64_t* n_cells,
+                           const float* const* J, const int64_t* ldj,
+                           const float* const* m_dust,
+                           float* const* T, const int64_t* ldt,
+                           float* const* L, const int64_t* ldl,
+                           dust_counters* counters, void* stream);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char* dust_last_error(void);

@@ -92,8 +92,9 @@ def lib():
                               ctypes.POINTER(_vp)],
         "dust_batch_launch": [_vp, _vp],
         "dust_batch_info": [_vp, _vp, _vp],
+        "dust_batch_form": [_vp, _vp, _vp, _vp],
         "dust_batch_destroy": [_vp],
-        "dust_probe_alu": [_i32, _i32, _i32, _vp, _vp],
+        "dust_batch_run": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -101,18 +102,6 @@ def lib():
         f.argtypes = args
     _lib = L
     return L
-
-
-# ALU throughput probes (dust_probe_alu kinds).
-PROBE_EXP2, PROBE_RCP, PROBE_FMA, PROBE_EXP2_FMA, PROBE_TERM = 0, 1, 2, 3, 4
-
-
-def probe_alu(kind, blocks, iters, out, stream=None):
-    """Launch one ALU throughput probe; `out` is a float32 device tensor of at
-    least 256 * blocks elements (one value per thread)."""
-    import torch
-    po = _vec(out, 256 * max(int(blocks), 0), "out", torch.float32)
-    _check(lib().dust_probe_alu(int(kind), int(blocks), int(iters), po, _stream(stream)))
 
 
 def last_error() -> str:
@@ -307,34 +296,55 @@ class Plan:
         return H, T, L
 
 
+def _grid_arrays(plans, J, m_dust, T, L):
+    """The per-grid host arrays of a batched call, after the binding's checks
+    (every tensor covers its grid's rows, on the plans' device)."""
+    n = len(plans)
+    arr = lambda typ, vals: (typ * n)(*vals)
+    hp = arr(_vp, [p.handle.value for p in plans])
+    nc = arr(_i64, [j.shape[0] for j in J])
+    pj, ldj, pt, ldt, pl, ldl = [], [], [], [], [], []
+    for p, j, t, l in zip(plans, J, T, L):
+        rows = j.shape[0]
+        a, b = _rows(j, p.n_lambda, "J", rows, p.device); pj.append(a.value or 0); ldj.append(b)
+        a, b = _rows(t, p.n_grains, "T", rows, p.device); pt.append(a.value or 0); ldt.append(b)
+        a, b = _rows(l, p.n_lambda, "L", rows, p.device); pl.append(a.value or 0); ldl.append(b)
+    pm = [_masses(m, j.shape[0], p.device).value or 0 for p, m, j in zip(plans, m_dust, J)]
+    return (hp, nc, arr(_vp, pj), arr(_i64, ldj), arr(_vp, pm), arr(_vp, pt),
+            arr(_i64, ldt), arr(_vp, pl), arr(_i64, ldl))
+
+
+def _as_vp(a):
+    return [ctypes.cast(x, _vp) for x in a]
+
+
+def batch_run(plans: Sequence[Plan], J, m_dust, T, L, counters=None, stream=None):
+    """One-shot batched launch (dust_batch_run): absorb -> solve -> emit for
+    every grid in one kernel, nothing kept."""
+    if not (len(plans) == len(J) == len(m_dust) == len(T) == len(L)):
+        raise ValueError("plans, J, m_dust, T and L must have one entry per grid")
+    a = _grid_arrays(plans, J, m_dust, T, L)
+    pc = _counters(counters, plans[0].device if plans else None)
+    v = _as_vp(a)
+    _check(lib().dust_batch_run(v[0], len(plans), v[1], v[2], v[3], v[4], v[5], v[6], v[7],
+                                v[8], pc, _stream(stream)))
+
+
 class Batch:
     """Many grids in one launch recorded in a HIP graph (dust_batch)."""
 
     def __init__(self, plans: Sequence[Plan], J, m_dust, T, L, counters=None, autotune=True,
                  refresh_plans=False):
-        n = len(plans)
-        arr = lambda typ, vals: (typ * n)(*vals)
+        if not (len(plans) == len(J) == len(m_dust) == len(T) == len(L)):
+            raise ValueError("plans, J, m_dust, T and L must have one entry per grid")
         self._plans = list(plans)
         self._bufs = (list(J), list(m_dust), list(T), list(L), counters)
-        hp = arr(_vp, [p.handle.value for p in plans])
-        nc = arr(_i64, [j.shape[0] for j in J])
-        pj, ldj, pt, ldt, pl, ldl = [], [], [], [], [], []
-        for p, j, t, l in zip(plans, J, T, L):
-            rows = j.shape[0]
-            a, b = _rows(j, p.n_lambda, "J", rows, p.device); pj.append(a.value or 0); ldj.append(b)
-            a, b = _rows(t, p.n_grains, "T", rows, p.device); pt.append(a.value or 0); ldt.append(b)
-            a, b = _rows(l, p.n_lambda, "L", rows, p.device); pl.append(a.value or 0); ldl.append(b)
-        pm = [_masses(m, j.shape[0], p.device).value or 0 for p, m, j in zip(plans, m_dust, J)]
+        self._arrays = _grid_arrays(plans, J, m_dust, T, L)
         pc = _counters(counters, plans[0].device if plans else None)
-        self._arrays = (hp, nc, arr(_vp, pj), arr(_i64, ldj), arr(_vp, pm), arr(_vp, pt),
-                        arr(_i64, ldt), arr(_vp, pl), arr(_i64, ldl))
         h = _vp()
-        a = self._arrays
-        _check(lib().dust_batch_create(ctypes.cast(a[0], _vp), n, ctypes.cast(a[1], _vp),
-                                       ctypes.cast(a[2], _vp), ctypes.cast(a[3], _vp),
-                                       ctypes.cast(a[4], _vp), ctypes.cast(a[5], _vp),
-                                       ctypes.cast(a[6], _vp), ctypes.cast(a[7], _vp),
-                                       ctypes.cast(a[8], _vp), pc,
+        v = _as_vp(self._arrays)
+        _check(lib().dust_batch_create(v[0], len(plans), v[1], v[2], v[3], v[4], v[5], v[6],
+                                       v[7], v[8], pc,
                                        (BATCH_AUTOTUNE if autotune else 0) |
                                        (BATCH_REFRESH_PLANS if refresh_plans else 0),
                                        ctypes.byref(h)))
@@ -348,6 +358,14 @@ class Batch:
         ni = _i64()
         _check(lib().dust_batch_info(self._h, ctypes.byref(tc), ctypes.byref(ni)))
         return {"cells_per_tile": tc.value, "n_items": ni.value}
+
+    def form(self):
+        """(cells per tile, grain tiles per wave, work-queue workgroups per CU
+        or 0 for one workgroup per item)."""
+        tc, ntw, pc = _i32(), _i32(), _i32()
+        _check(lib().dust_batch_form(self._h, ctypes.byref(tc), ctypes.byref(ntw),
+                                     ctypes.byref(pc)))
+        return tc.value, ntw.value, pc.value
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

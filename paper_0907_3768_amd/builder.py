@@ -1,9 +1,11 @@
 """Compile libdust.so for gfx950 with hipcc (in-tree, no JIT cache).
 
 Every translation unit under csrc/ is compiled to an object in parallel and
-linked into paper_0907_3768_amd/libdust.so.  Packed FP32 instructions are
-disabled for the device code (-packed-fp32-ops): the kernels are written
-with ordinary scalar float arithmetic.
+linked into paper_0907_3768_amd/libdust.so.  The measurement-only ALU probes
+under measure/ become a library of their own, libdust_probe.so, which only
+the benchmark loads.  Packed FP32 instructions are disabled for the device
+code (-packed-fp32-ops): the kernels are written with ordinary scalar float
+arithmetic.
 """
 from __future__ import annotations
 
@@ -18,7 +20,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
+MEASURE = os.path.join(HERE, "measure")
 LIB = os.path.join(HERE, "libdust.so")
+PROBE_LIB = os.path.join(HERE, "libdust_probe.so")
 ARCH = os.environ.get("DUST_OFFLOAD_ARCH", "gfx950")
 
 
@@ -35,15 +39,13 @@ def flags():
             "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    objdir = os.path.join(ROOT, "_build", "obj")
-    os.makedirs(objdir, exist_ok=True)
+def _compile_link(srcs, lib, objdir, extra_inc, verbose):
     cc = hipcc()
+    os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [cc] + flags() + ["-c", src, "-o", obj]
+        cmd = [cc] + flags() + extra_inc + ["-c", src, "-o", obj]
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
         out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
         if r.returncode != 0:
@@ -55,12 +57,22 @@ def build(verbose: bool = False) -> str:
     workers = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(compile_one, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Build libdust.so and the benchmark's libdust_probe.so; returns the
+    path of libdust.so."""
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    _compile_link(srcs, LIB, os.path.join(ROOT, "_build", "obj"), [], verbose)
+    _compile_link(sorted(glob.glob(os.path.join(MEASURE, "*.hip"))), PROBE_LIB,
+                  os.path.join(ROOT, "_build", "obj_probe"), ["-I", MEASURE], verbose)
     return LIB
 
 

@@ -14,8 +14,11 @@
 // chosen by timing candidates on the bound buffers (autotuner); the chosen
 // launch (with the counter reset, and optionally every plan's refresh) is
 // recorded once into a HIP graph and replayed by dust_batch_launch.
+// dust_batch_run is the one-shot form: it builds the same work list, copies
+// it to a stream-ordered device allocation and launches once.
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <map>
@@ -50,10 +53,13 @@ __global__ void reset_counter_kernel(unsigned int* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
 }
 
+// Resident waves per SIMD as for the one-workgroup-per-item kernel below:
+// without the hint the compiler gives the loop's body more registers, and
+// fewer waves per SIMD leave the emission's latencies exposed.
 template <int TC, int NTW>
-__global__ __launch_bounds__(256) void batch_kernel(const GridArgs* __restrict__ grids,
-                                                    const int2* __restrict__ items, int n_items,
-                                                    unsigned int* counter, dust_counters* cnt) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTW <= 2 ? 6 : 5, 8))) void batch_kernel(
+    const GridArgs* __restrict__ grids, const int2* __restrict__ items, int n_items,
+    unsigned int* counter, dust_counters* cnt) {
     extern __shared__ float sTile[];  // fused_lds_bytes(TC, Sp max, Stage<BATCH_KC>::BYTES)
     __shared__ int sItem;
     for (;;) {
@@ -129,6 +135,90 @@ KernelFn kernel_for(int tc, int ntw, bool persistent) {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, Candidate> g_tune_cache;
 
+// Default launch: one workgroup per 16-cell item, as many grain tiles per
+// wave as the largest grid needs (at most two; more take passes).
+Candidate default_candidate(int sp_max) {
+    const int need = (sp_max / 16 + 3) / 4;
+    return Candidate{16, 0, need < 2 ? need : 2};
+}
+
+// Whether a candidate fits the batch: its LDS (sized for the largest grid)
+// in one workgroup and, times its resident workgroups, in one CU; and no more
+// grain tiles per wave than the largest grid needs.
+bool candidate_fits(const Candidate& c, int sp_max, int max_lds) {
+    const size_t lds = fused_lds_bytes(c.tc, sp_max, Stage<BATCH_KC>::BYTES);
+    if (c.ntw > 1 && c.ntw / 2 >= (sp_max / 16 + 3) / 4) return false;
+    return lds <= (size_t)max_lds && lds * std::max(c.per_cu, 1) <= 160u * 1024u;
+}
+
+// Candidate named by the environment variable DUST_BATCH_CANDIDATE as
+// "tc,ntw,per_cu" (a test hook that pins the launch form); returns 0 when
+// the variable is unset, 1 with *c set, -1 when it is malformed or does not
+// name a candidate form.
+int forced_candidate(Candidate* c) {
+    const char* s = getenv("DUST_BATCH_CANDIDATE");
+    if (!s || !*s) return 0;
+    int tc = 0, ntw = 0, per_cu = -1;
+    if (sscanf(s, "%d,%d,%d", &tc, &ntw, &per_cu) != 3) return -1;
+    if ((tc != 16 && tc != 32) || (ntw != 1 && ntw != 2 && ntw != 4) ||
+        (per_cu != 0 && per_cu != 2 && per_cu != 4 && per_cu != 6))
+        return -1;
+    *c = Candidate{tc, per_cu, ntw};
+    return 1;
+}
+
+// Host side shared by dust_batch_create and dust_batch_run: checks every
+// grid's arguments and fills the per-grid launch arguments, cell counts and
+// costs; *sp_max receives the largest padded grain count, *tiles16 the number
+// of 16-cell tiles.
+dust_status bind_grids(dust_plan* const* plans, int32_t n_grids, const int64_t* n_cells,
+                       const float* const* J, const int64_t* ldj, const float* const* m_dust,
+                       float* const* T, const int64_t* ldt, float* const* L,
+                       const int64_t* ldl, dust_counters* counters, std::vector<GridArgs>* args,
+                       std::vector<int64_t>* C, std::vector<double>* cost, int* sp_max,
+                       int64_t* tiles16, int* device) {
+    if (n_grids < 1) return set_error(DUST_EINVAL, "n_grids must be >= 1");
+    if (!plans || !n_cells || !J || !ldj || !m_dust || !T || !ldt || !L || !ldl)
+        return set_error(DUST_EINVAL, "a per-grid array is NULL");
+    if (counters && ((uintptr_t)counters & 7u))
+        return set_error(DUST_EINVAL, "counters must be 8-byte aligned");
+    args->assign(n_grids, GridArgs{});
+    C->assign(n_grids, 0);
+    cost->assign(n_grids, 0.0);
+    *sp_max = 16;
+    *tiles16 = 0;
+    for (int g = 0; g < n_grids; ++g) {
+        const dust_plan* p = plans[g];
+        if (!p) return set_error(DUST_EINVAL, "plans[" + std::to_string(g) + "] is NULL");
+        if (p->opt.mode != DUST_MIXED || p->opt.f32_lookup)
+            return set_error(DUST_EUNSUPPORTED,
+                             "batched launches take DUST_MIXED plans with the FP64 lookup");
+        if (n_cells[g] < 0 || n_cells[g] > ((int64_t)1 << 36))
+            return set_error(DUST_EINVAL, "n_cells out of range");
+        const int64_t c = n_cells[g];
+        if (c > 0) {
+            if (!J[g] || !T[g] || !L[g]) return set_error(DUST_EINVAL, "a J/T/L pointer is NULL");
+            if (ldj[g] < p->NL || ldt[g] < p->S || ldl[g] < p->NL)
+                return set_error(DUST_EINVAL, "a leading dimension is smaller than its row");
+            if (((uintptr_t)J[g] | (uintptr_t)T[g] | (uintptr_t)L[g] |
+                 (uintptr_t)m_dust[g]) & 3u)
+                return set_error(DUST_EINVAL, "buffers must be 4-byte aligned");
+        }
+        (*args)[g] = GridArgs{p->view, c, J[g], ldj[g], m_dust[g], T[g], ldt[g], L[g], ldl[g]};
+        (*C)[g] = c;
+        (*cost)[g] = (double)p->NL * p->S;
+        *sp_max = std::max(*sp_max, p->Sp);
+        *tiles16 += (c + 15) / 16;
+    }
+    if (*tiles16 > (int64_t)1 << 30) return set_error(DUST_EUNSUPPORTED, "too many tiles");
+    hipError_t e;
+    if ((e = hipGetDevice(device)) != hipSuccess) return hip_error(e, "hipGetDevice");
+    for (int g = 0; g < n_grids; ++g)
+        if (plans[g]->device != *device)
+            return set_error(DUST_EINVAL, "every plan must belong to the current device");
+    return DUST_OK;
+}
+
 }  // namespace
 }  // namespace dust
 
@@ -200,6 +290,12 @@ std::vector<int2> build_items(const std::vector<int64_t>& C, const std::vector<d
     return items;
 }
 
+int max_lds_bytes(int dev) {
+    int max_lds = 65536;
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    return max_lds;
+}
+
 }  // namespace
 }  // namespace dust
 
@@ -217,49 +313,27 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     const bool refresh = (flags & DUST_BATCH_REFRESH_PLANS) != 0;
     if (!out) return set_error(DUST_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n_grids < 1) return set_error(DUST_EINVAL, "n_grids must be >= 1");
-    if (!plans || !n_cells || !J || !ldj || !m_dust || !T || !ldt || !L || !ldl)
-        return set_error(DUST_EINVAL, "a per-grid array is NULL");
-    if (counters && ((uintptr_t)counters & 7u))
-        return set_error(DUST_EINVAL, "counters must be 8-byte aligned");
     if (flags & ~(DUST_BATCH_AUTOTUNE | DUST_BATCH_REFRESH_PLANS))
         return set_error(DUST_EINVAL, "unknown batch flags");
-    std::vector<GridArgs> args(n_grids);
-    std::vector<int64_t> C(n_grids);
-    std::vector<double> cost(n_grids);
-    int sp_max = 16;
+    std::vector<GridArgs> args;
+    std::vector<int64_t> C;
+    std::vector<double> cost;
+    int sp_max = 16, dev = 0;
     int64_t total16 = 0;
-    for (int g = 0; g < n_grids; ++g) {
-        const dust_plan* p = plans[g];
-        if (!p) return set_error(DUST_EINVAL, "plans[" + std::to_string(g) + "] is NULL");
-        if (p->opt.mode != DUST_MIXED || p->opt.f32_lookup)
-            return set_error(DUST_EUNSUPPORTED,
-                             "batched launches take DUST_MIXED plans with the FP64 lookup");
-        if (n_cells[g] < 0 || n_cells[g] > ((int64_t)1 << 36))
-            return set_error(DUST_EINVAL, "n_cells out of range");
-        const int64_t c = n_cells[g];
-        if (c > 0) {
-            if (!J[g] || !T[g] || !L[g]) return set_error(DUST_EINVAL, "a J/T/L pointer is NULL");
-            if (ldj[g] < p->NL || ldt[g] < p->S || ldl[g] < p->NL)
-                return set_error(DUST_EINVAL, "a leading dimension is smaller than its row");
-            if (((uintptr_t)J[g] | (uintptr_t)T[g] | (uintptr_t)L[g] |
-                 (uintptr_t)m_dust[g]) & 3u)
-                return set_error(DUST_EINVAL, "buffers must be 4-byte aligned");
-        }
-        args[g] = GridArgs{p->view, c, J[g], ldj[g], m_dust[g], T[g], ldt[g], L[g], ldl[g]};
-        C[g] = c;
-        cost[g] = (double)p->NL * p->S;
-        sp_max = std::max(sp_max, p->Sp);
-        total16 += (c + 15) / 16;
-    }
-    if (total16 > (int64_t)1 << 30) return set_error(DUST_EUNSUPPORTED, "too many tiles");
+    dust_status st = bind_grids(plans, n_grids, n_cells, J, ldj, m_dust, T, ldt, L, ldl, counters,
+                                &args, &C, &cost, &sp_max, &total16, &dev);
+    if (st != DUST_OK) return st;
+    const int max_lds = max_lds_bytes(dev);
+    Candidate forced{};
+    const int force = forced_candidate(&forced);
+    if (force < 0)
+        return set_error(DUST_EINVAL,
+                         "DUST_BATCH_CANDIDATE must be \"tc,ntw,per_cu\" with tc 16 or 32, "
+                         "ntw 1, 2 or 4, per_cu 0, 2, 4 or 6");
+    if (force > 0 && !candidate_fits(forced, sp_max, max_lds))
+        return set_error(DUST_EUNSUPPORTED, "DUST_BATCH_CANDIDATE does not fit this batch");
 
-    int dev = 0;
     hipError_t e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_error(e, "hipGetDevice");
-    for (int g = 0; g < n_grids; ++g)
-        if (plans[g]->device != dev)
-            return set_error(DUST_EINVAL, "every plan must belong to the current device");
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
         return hip_error(e, "hipGetDeviceProperties");
@@ -288,24 +362,22 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
         return hip_error(e, "hipMemcpy (batch)");
     }
 
-    int max_lds = 65536;
-    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    // Candidate tile shapes.  32-cell tiles need twice the LDS per workgroup;
-    // a workgroup may hold at most 64 KiB and a CU 160 KiB.
+    // Candidate launches: 16- or 32-cell tiles (32 needs twice the LDS per
+    // workgroup; a workgroup may hold at most 64 KiB and a CU 160 KiB), one
+    // or more grain tiles per wave, one workgroup per item or a work queue
+    // with 2, 4 or 6 resident workgroups per CU.
     std::vector<Candidate> cands;
-    const int ntw_need = (sp_max / 16 + 3) / 4;
     for (int tc : {16, 32})
-        for (int ntw : {1, 2, 4}) {
-            if (ntw > 1 && ntw / 2 >= ntw_need) continue;  // no more depth than needed
-            for (int per_cu : {0, 2, 4}) {
-                const size_t lds = fused_lds_bytes(tc, sp_max, Stage<BATCH_KC>::BYTES);
-                if (lds <= (size_t)max_lds && lds * std::max(per_cu, 1) <= 160u * 1024u)
-                    cands.push_back(Candidate{tc, per_cu, ntw});
+        for (int ntw : {1, 2, 4})
+            for (int per_cu : {0, 2, 4, 6}) {
+                const Candidate c{tc, per_cu, ntw};
+                if (candidate_fits(c, sp_max, max_lds)) cands.push_back(c);
             }
-        }
-    Candidate best{16, 0, ntw_need < 2 ? ntw_need : 2};
+    Candidate best = default_candidate(sp_max);
     const bool verbose = getenv("DUST_LOG") != nullptr;
-    if (autotune && !cands.empty()) {
+    if (force > 0) {
+        best = forced;
+    } else if (autotune && !cands.empty()) {
         double mean_nl = 0.0;
         for (int g = 0; g < n_grids; ++g) mean_nl += plans[g]->NL;
         mean_nl /= n_grids;
@@ -351,7 +423,7 @@ dust_status dust_batch_create(dust_plan* const* plans, int32_t n_grids, const in
     }
     b->cand = best;
 
-    // The plans' refreshes as four batched launches (one per stage, every
+    // The plans' refreshes as three batched launches (one per stage, every
     // distinct plan in each), then the chosen batched kernel, recorded once.
     if (refresh) {
         std::vector<const dust_plan*> uniq;
@@ -418,12 +490,64 @@ dust_status dust_batch_info(const dust_batch* b, int32_t* cells_per_tile, int64_
     return DUST_OK;
 }
 
+dust_status dust_batch_form(const dust_batch* b, int32_t* cells_per_tile,
+                            int32_t* tiles_per_wave, int32_t* per_cu) {
+    clear_error();
+    if (!b) return set_error(DUST_EINVAL, "batch is NULL");
+    if (cells_per_tile) *cells_per_tile = b->cand.tc;
+    if (tiles_per_wave) *tiles_per_wave = b->cand.ntw;
+    if (per_cu) *per_cu = b->cand.per_cu;
+    return DUST_OK;
+}
+
 dust_status dust_batch_destroy(dust_batch* b) {
     clear_error();
     if (!b) return DUST_OK;
     hipError_t e = hipDeviceSynchronize();
     free_batch(b);
     return e == hipSuccess ? DUST_OK : hip_error(e, "hipDeviceSynchronize");
+}
+
+dust_status dust_batch_run(dust_plan* const* plans, int32_t n_grids, const int64_t* n_cells,
+                           const float* const* J, const int64_t* ldj,
+                           const float* const* m_dust, float* const* T, const int64_t* ldt,
+                           float* const* L, const int64_t* ldl, dust_counters* counters,
+                           void* stream) {
+    clear_error();
+    std::vector<GridArgs> args;
+    std::vector<int64_t> C;
+    std::vector<double> cost;
+    int sp_max = 16, dev = 0;
+    int64_t total16 = 0;
+    dust_status st = bind_grids(plans, n_grids, n_cells, J, ldj, m_dust, T, ldt, L, ldl, counters,
+                                &args, &C, &cost, &sp_max, &total16, &dev);
+    if (st != DUST_OK) return st;
+    if (total16 == 0) return DUST_OK;
+    const Candidate c = default_candidate(sp_max);
+    const std::vector<int2> items = build_items(C, cost, c.tc);
+    // one staging block: the grids' launch arguments, then the item list
+    const size_t args_bytes = (sizeof(GridArgs) * (size_t)n_grids + 255) / 256 * 256;
+    const size_t bytes = args_bytes + sizeof(int2) * items.size();
+    std::vector<char> host(bytes);
+    memcpy(host.data(), args.data(), sizeof(GridArgs) * (size_t)n_grids);
+    memcpy(host.data() + args_bytes, items.data(), sizeof(int2) * items.size());
+    const hipStream_t sm = (hipStream_t)stream;
+    void* d = nullptr;
+    hipError_t e = hipMallocAsync(&d, bytes, sm);
+    if (e != hipSuccess) return hip_error(e, "hipMallocAsync (batch work list)");
+    // from pageable memory: the call returns once `host` has been staged
+    e = hipMemcpyAsync(d, host.data(), bytes, hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) {
+        const size_t lds = fused_lds_bytes(c.tc, sp_max, Stage<BATCH_KC>::BYTES);
+        hipLaunchKernelGGL(kernel_for(c.tc, c.ntw, false), dim3((unsigned)items.size()), dim3(256),
+                           lds, sm, (const GridArgs*)d,
+                           reinterpret_cast<const int2*>((char*)d + args_bytes), (int)items.size(),
+                           nullptr, counters);
+        e = hipGetLastError();
+    }
+    const hipError_t ef = hipFreeAsync(d, sm);
+    if (e != hipSuccess) return hip_error(e, "batch run");
+    return ef == hipSuccess ? DUST_OK : hip_error(ef, "hipFreeAsync (batch work list)");
 }
 
 }  // extern "C"

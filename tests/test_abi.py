@@ -170,6 +170,23 @@ def test_binding_constants_match_header():
     assert ctypes.sizeof(dust.SolveExt) == 24 and "warm_start" in ext and "ldq" in ext
 
 
+def test_probe_is_not_in_the_method_library():
+    """The ALU throughput probes are measurement code: they live in their own
+    library, which only the benchmark loads."""
+    out = subprocess.run(["nm", "-D", "--defined-only", dust.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    assert "probe" not in out
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_0907_3768_amd import builder
+    if not os.path.exists(builder.PROBE_LIB):
+        dust.build()
+    import bench
+    return bench.probe_lib()
+
+
 @pytest.mark.parametrize("kind,blocks,iters,null_out", [
     (0, 0, 16, False),         # no blocks
     (0, 1 << 21, 16, False),   # too many blocks
@@ -178,16 +195,38 @@ def test_binding_constants_match_header():
     (9, 4, 16, False),         # unknown kind
     (-1, 4, 16, False),
 ])
-def test_probe_alu_rejects(L, kind, blocks, iters, null_out):
+def test_probe_alu_rejects(P, kind, blocks, iters, null_out):
     """The ALU probe checks its arguments before any HIP call."""
     out = None if null_out else ctypes.c_void_p(16)  # never dereferenced: the call fails first
-    code = L.dust_probe_alu(kind, blocks, iters, out, None)
-    assert code == dust.DUST_EINVAL
-    assert L.dust_last_error()
+    assert P.alu_probe_run(kind, blocks, iters, out, None) == -1
 
 
-def test_binding_probe_constants_match_header():
-    text = open(os.path.join(ROOT, "include", "dust.h")).read()
-    for name, value in (("EXP2", 0), ("RCP", 1), ("FMA", 2), ("EXP2_FMA", 3), ("TERM", 4)):
-        assert re.search(rf"DUST_PROBE_{name} = {value}\b", text)
-        assert getattr(dust, f"PROBE_{name}") == value
+def test_probe_constants_match_header():
+    import bench
+    text = open(os.path.join(ROOT, "paper_0907_3768_amd", "measure", "alu_probe.h")).read()
+    for name, value in bench.PROBE_KINDS:
+        key = {"exp2": "EXP2", "rcp": "RCP", "fma": "FMA", "exp2+fma": "EXP2_FMA",
+               "term": "TERM"}[name]
+        assert re.search(rf"ALU_PROBE_{key} = {value}\b", text)
+
+
+def test_batch_calls_reject_bad_arguments(L):
+    """dust_batch_create and dust_batch_run check their arguments before any
+    HIP call."""
+    n = ctypes.c_void_p()
+    nc = (ctypes.c_int64 * 1)(4)
+    z = (ctypes.c_void_p * 1)(None)
+    ld = (ctypes.c_int64 * 1)(8)
+    args = [ctypes.cast(z, ctypes.c_void_p), 1, ctypes.cast(nc, ctypes.c_void_p)] + \
+           [ctypes.cast(x, ctypes.c_void_p) for x in (z, ld, z, z, ld, z, ld)] + [None]
+    assert L.dust_batch_run(*args, None) == dust.DUST_EINVAL       # plans[0] is NULL
+    assert b"NULL" in L.dust_last_error()
+    assert L.dust_batch_create(*args, 0, ctypes.byref(n)) == dust.DUST_EINVAL
+    args[1] = 0
+    assert L.dust_batch_run(*args, None) == dust.DUST_EINVAL       # no grids
+    assert L.dust_batch_create(*args, 0, ctypes.byref(n)) == dust.DUST_EINVAL
+    args[1] = 1
+    args[10] = ctypes.c_void_p(12)                                  # misaligned counters
+    assert L.dust_batch_run(*args, None) == dust.DUST_EINVAL
+    assert L.dust_batch_create(*args, 9, ctypes.byref(n)) == dust.DUST_EINVAL  # bad flags
+    assert L.dust_batch_form(None, None, None, None) == dust.DUST_EINVAL

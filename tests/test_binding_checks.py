@@ -99,7 +99,15 @@ def test_extra_heating_rows_checked():
 
 
 def test_probe_output_must_be_device_memory():
+    import bench
     with pytest.raises(TypeError):
-        dust.probe_alu(dust.PROBE_FMA, 4, 16, FakeCuda((1024,), cuda=False))
+        bench.probe_launch(None, 2, 4, 16, FakeCuda((1024,), cuda=False))
     with pytest.raises(ValueError):
-        dust.probe_alu(dust.PROBE_FMA, 4, 16, FakeCuda((1023,)))
+        bench.probe_launch(None, 2, 4, 16, FakeCuda((1023,)))
+
+
+def test_batched_calls_need_one_entry_per_grid():
+    with pytest.raises(ValueError):
+        dust.batch_run([], [FakeCuda((4, 8))], [None], [], [])
+    with pytest.raises(ValueError):
+        dust.Batch([], [FakeCuda((4, 8))], [None], [], [])

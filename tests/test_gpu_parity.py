@@ -171,19 +171,21 @@ def test_zero_field_and_nan(dev, mode):
                              Lh[keep])
 
 
-@pytest.mark.parametrize("f32,bound", [(False, 3e-7), (True, 4e-6)])
-def test_mixed_lookup_precision(dev, f32, bound):
+@pytest.mark.parametrize("f32,ltab_n,bound", [(False, 0, 3e-7), (True, 0, 4e-6),
+                                               (False, 4096, 3e-7)])
+def test_mixed_lookup_precision(dev, f32, ltab_n, bound):
     """The mixed temperature step alone: given the oracle's FP64 heating
     rounded to FP32, T must match the oracle's root of Eq. 7 for exactly that
     H to the lookup's own error (FP64 inverse table: interpolation ~1e-9,
-    plus FP32 rounding of T; FP32 lookup: FP32 rounding of ln H')."""
+    plus FP32 rounding of T; FP32 lookup: FP32 rounding of ln H').  With the
+    default 1024 table temperatures and with 4096."""
     w = synth.WORKLOADS["small-1024x120x20"]
     g = w.grid()
     J, _ = _inputs(g, 512, 23, dev)
     H64 = oracle.heating(_host(J).astype(np.float64), g.c_abs, g.dlam)
     H32 = H64.astype(np.float32)
     T_ref = oracle.temperature(H32.astype(np.float64), g.lam, g.dlam, g.c_abs, g.size)
-    plan = dust.Plan(g, "mixed", f32_lookup=f32)
+    plan = dust.Plan(g, "mixed", f32_lookup=f32, ltab_n=ltab_n)
     cnt = dust.new_counters(dev)
     T = plan.solve(torch.as_tensor(H32, device=dev), counters=cnt)
     torch.cuda.synchronize()
@@ -387,19 +389,23 @@ def test_deterministic_and_prepare(dev, mode):
 
 # --------------------------------------------------------------------------- full sizes, sampled
 
-FULL = [("plain-262144x250x80", "plain"), ("plain-262144x250x80", "mixed"),
-        ("mixed-1048576x500x128", "mixed"), ("full-4194304x1000x240", "mixed")]
+# (workload, mode, table temperatures of the mixed form; 0 = the default 1024).
+# The million-cell workload also runs with the 4096 log-spaced table
+# temperatures its configuration states.
+FULL = [("plain-262144x250x80", "plain", 0), ("plain-262144x250x80", "mixed", 0),
+        ("mixed-1048576x500x128", "mixed", 0), ("mixed-1048576x500x128", "mixed", 4096),
+        ("full-4194304x1000x240", "mixed", 0)]
 
 
-@pytest.mark.parametrize("name,mode", FULL)
-def test_full_size_sampled(dev, name, mode):
+@pytest.mark.parametrize("name,mode,ltab_n", FULL)
+def test_full_size_sampled(dev, name, mode, ltab_n):
     w = synth.WORKLOADS[name]
     g = w.grid()
-    say(f"full size {name} mode={mode}: generating J")
+    say(f"full size {name} mode={mode} ltab_n={ltab_n}: generating J")
     p = w.cells()
     J = synth.radiation_field(p, g.lam, device=dev)
     m = torch.as_tensor(p.m_dust, dtype=torch.float32, device=dev)
-    plan = dust.Plan(g, mode)
+    plan = dust.Plan(g, mode, ltab_n=ltab_n)
     cnt = dust.new_counters(dev)
     say(f"full size {name} mode={mode}: running")
     if mode == "plain":
@@ -407,7 +413,9 @@ def test_full_size_sampled(dev, name, mode):
     else:
         T, L = plan.fused(J, m, counters=cnt)
     torch.cuda.synchronize()
-    rows = strided_rows(w.n_cells, 192)
+    # the 4096-cell strided subsample of the million-cell workloads, 192
+    # cells of the others
+    rows = strided_rows(w.n_cells, 4096 if w.n_cells >= (1 << 20) else 192)
     idx = torch.as_tensor(rows, device=dev)
     say(f"full size {name} mode={mode}: oracle on {len(rows)} cells")
     res = check_against_oracle(g, _host(J[idx]), p.m_dust[rows], _host(T[idx]), _host(L[idx]))
