@@ -275,6 +275,28 @@ dust_status dust_batch_run(dust_plan* const* plans, int32_t n_grids,
                            float* const* L, const int64_t* ldl,
                            dust_counters* counters, void* stream);
 
+/* dust_batch_run for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid hipMalloc): the same arguments, checks,
+ * kernel and results, but the work list goes into a fixed array of 4 MiB
+ * that the library reserves on every device it runs on when it is loaded
+ * (a static device array, held until the process ends), instead of a
+ * stream-ordered allocation.  It calls no allocating routine.  Limits,
+ * checked before any HIP call (DUST_EINVAL, nothing enqueued): at most 256
+ * grids, and at most about 5.1e5 16-cell tiles over all grids (the exact
+ * figure is in the error text).  The array holds only what each call writes
+ * before its kernel reads it (no counter or partial result carries over), so
+ * nothing needs clearing between calls.  All calls on one device share the
+ * array: calls ordered on one stream are safe, calls that may overlap (other
+ * streams, other host threads) race on it.  Not capturable into a HIP graph
+ * (the work list is copied from pageable host memory). */
+dust_status dust_batch_run_noalloc(dust_plan* const* plans, int32_t n_grids,
+                                   const int64_t* n_cells,
+                                   const float* const* J, const int64_t* ldj,
+                                   const float* const* m_dust,
+                                   float* const* T, const int64_t* ldt,
+                                   float* const* L, const int64_t* ldl,
+                                   dust_counters* counters, void* stream);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* dust_last_error(void);
 

@@ -95,6 +95,8 @@ def lib():
         "dust_batch_form": [_vp, _vp, _vp, _vp],
         "dust_batch_destroy": [_vp],
         "dust_batch_run": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+        "dust_batch_run_noalloc": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -318,16 +320,20 @@ def _as_vp(a):
     return [ctypes.cast(x, _vp) for x in a]
 
 
-def batch_run(plans: Sequence[Plan], J, m_dust, T, L, counters=None, stream=None):
+def batch_run(plans: Sequence[Plan], J, m_dust, T, L, counters=None, stream=None,
+              no_alloc=False):
     """One-shot batched launch (dust_batch_run): absorb -> solve -> emit for
-    every grid in one kernel, nothing kept."""
+    every grid in one kernel, nothing kept.  no_alloc: dust_batch_run_noalloc
+    (the work list in the library's fixed device array; calls that may
+    overlap on one device race)."""
     if not (len(plans) == len(J) == len(m_dust) == len(T) == len(L)):
         raise ValueError("plans, J, m_dust, T and L must have one entry per grid")
     a = _grid_arrays(plans, J, m_dust, T, L)
     pc = _counters(counters, plans[0].device if plans else None)
     v = _as_vp(a)
-    _check(lib().dust_batch_run(v[0], len(plans), v[1], v[2], v[3], v[4], v[5], v[6], v[7],
-                                v[8], pc, _stream(stream)))
+    f = lib().dust_batch_run_noalloc if no_alloc else lib().dust_batch_run
+    _check(f(v[0], len(plans), v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], pc,
+             _stream(stream)))
 
 
 class Batch:

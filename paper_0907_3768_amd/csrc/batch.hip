@@ -28,6 +28,14 @@
 
 #include "fused_body.h"
 
+// Work-list storage of dust_batch_run_noalloc: one array per device, reserved
+// when the library is loaded and held until the process ends.  Host code
+// never uses the symbol as an address (on the host it is only a stand-in):
+// scratch_ptr() asks the runtime for the current device's copy once and keeps
+// it, and every copy and kernel argument uses that pointer.
+static constexpr size_t SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
 namespace dust {
 namespace {
 
@@ -290,6 +298,56 @@ std::vector<int2> build_items(const std::vector<int64_t>& C, const std::vector<d
     return items;
 }
 
+// (the static work-list array `scratch` is declared at file scope above)
+constexpr int SCRATCH_MAX_GRIDS = 256;
+
+// Bytes of a work list: the grids' launch arguments (padded to 256 bytes),
+// then the (grid, tile) items.
+size_t work_list_args_bytes(int n_grids) {
+    return (sizeof(GridArgs) * (size_t)n_grids + 255) / 256 * 256;
+}
+int64_t scratch_max_items() {
+    return (int64_t)((SCRATCH_BYTES - work_list_args_bytes(SCRATCH_MAX_GRIDS)) / sizeof(int2));
+}
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES];
+
+hipError_t scratch_ptr(int dev, void** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// Copies the work list (host staging) to `d` on `sm` and launches the
+// per-item kernel of the default form over it.
+hipError_t launch_work_list(const std::vector<GridArgs>& args, const std::vector<int2>& items,
+                            int sp_max, const Candidate& c, void* d, dust_counters* counters,
+                            hipStream_t sm) {
+    const size_t args_bytes = work_list_args_bytes((int)args.size());
+    const size_t bytes = args_bytes + sizeof(int2) * items.size();
+    std::vector<char> host(bytes);
+    memcpy(host.data(), args.data(), sizeof(GridArgs) * args.size());
+    memcpy(host.data() + args_bytes, items.data(), sizeof(int2) * items.size());
+    // from pageable memory: the call returns once `host` has been staged
+    hipError_t e = hipMemcpyAsync(d, host.data(), bytes, hipMemcpyHostToDevice, sm);
+    if (e != hipSuccess) return e;
+    const size_t lds = fused_lds_bytes(c.tc, sp_max, Stage<BATCH_KC>::BYTES);
+    hipLaunchKernelGGL(kernel_for(c.tc, c.ntw, false), dim3((unsigned)items.size()), dim3(256),
+                       lds, sm, (const GridArgs*)d,
+                       reinterpret_cast<const int2*>((char*)d + args_bytes), (int)items.size(),
+                       nullptr, counters);
+    return hipGetLastError();
+}
+
 int max_lds_bytes(int dev) {
     int max_lds = 65536;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
@@ -525,29 +583,51 @@ dust_status dust_batch_run(dust_plan* const* plans, int32_t n_grids, const int64
     if (total16 == 0) return DUST_OK;
     const Candidate c = default_candidate(sp_max);
     const std::vector<int2> items = build_items(C, cost, c.tc);
-    // one staging block: the grids' launch arguments, then the item list
-    const size_t args_bytes = (sizeof(GridArgs) * (size_t)n_grids + 255) / 256 * 256;
-    const size_t bytes = args_bytes + sizeof(int2) * items.size();
-    std::vector<char> host(bytes);
-    memcpy(host.data(), args.data(), sizeof(GridArgs) * (size_t)n_grids);
-    memcpy(host.data() + args_bytes, items.data(), sizeof(int2) * items.size());
     const hipStream_t sm = (hipStream_t)stream;
     void* d = nullptr;
-    hipError_t e = hipMallocAsync(&d, bytes, sm);
+    hipError_t e = hipMallocAsync(&d, work_list_args_bytes(n_grids) + sizeof(int2) * items.size(), sm);
     if (e != hipSuccess) return hip_error(e, "hipMallocAsync (batch work list)");
-    // from pageable memory: the call returns once `host` has been staged
-    e = hipMemcpyAsync(d, host.data(), bytes, hipMemcpyHostToDevice, sm);
-    if (e == hipSuccess) {
-        const size_t lds = fused_lds_bytes(c.tc, sp_max, Stage<BATCH_KC>::BYTES);
-        hipLaunchKernelGGL(kernel_for(c.tc, c.ntw, false), dim3((unsigned)items.size()), dim3(256),
-                           lds, sm, (const GridArgs*)d,
-                           reinterpret_cast<const int2*>((char*)d + args_bytes), (int)items.size(),
-                           nullptr, counters);
-        e = hipGetLastError();
-    }
+    e = launch_work_list(args, items, sp_max, c, d, counters, sm);
     const hipError_t ef = hipFreeAsync(d, sm);
     if (e != hipSuccess) return hip_error(e, "batch run");
     return ef == hipSuccess ? DUST_OK : hip_error(ef, "hipFreeAsync (batch work list)");
+}
+
+dust_status dust_batch_run_noalloc(dust_plan* const* plans, int32_t n_grids,
+                                   const int64_t* n_cells, const float* const* J,
+                                   const int64_t* ldj, const float* const* m_dust,
+                                   float* const* T, const int64_t* ldt, float* const* L,
+                                   const int64_t* ldl, dust_counters* counters, void* stream) {
+    clear_error();
+    // the limits of the static work-list array, before any HIP call
+    if (n_grids > SCRATCH_MAX_GRIDS)
+        return set_error(DUST_EINVAL, "dust_batch_run_noalloc takes at most " +
+                                          std::to_string(SCRATCH_MAX_GRIDS) + " grids");
+    if (n_grids >= 1 && n_cells) {
+        int64_t tiles = 0;
+        for (int g = 0; g < n_grids; ++g)
+            if (n_cells[g] > 0) tiles += (std::min<int64_t>(n_cells[g], (int64_t)1 << 36) + 15) / 16;
+        if (tiles > scratch_max_items())
+            return set_error(DUST_EINVAL, "dust_batch_run_noalloc takes at most " +
+                                              std::to_string(scratch_max_items()) +
+                                              " 16-cell tiles in all");
+    }
+    std::vector<GridArgs> args;
+    std::vector<int64_t> C;
+    std::vector<double> cost;
+    int sp_max = 16, dev = 0;
+    int64_t total16 = 0;
+    dust_status st = bind_grids(plans, n_grids, n_cells, J, ldj, m_dust, T, ldt, L, ldl, counters,
+                                &args, &C, &cost, &sp_max, &total16, &dev);
+    if (st != DUST_OK) return st;
+    if (total16 == 0) return DUST_OK;
+    void* d = nullptr;
+    hipError_t e = scratch_ptr(dev, &d);
+    if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress (work-list array)");
+    const Candidate c = default_candidate(sp_max);
+    e = launch_work_list(args, build_items(C, cost, c.tc), sp_max, c, d, counters,
+                         (hipStream_t)stream);
+    return e == hipSuccess ? DUST_OK : hip_error(e, "batch run (no allocation)");
 }
 
 }  // extern "C"

@@ -230,3 +230,20 @@ def test_batch_calls_reject_bad_arguments(L):
     assert L.dust_batch_run(*args, None) == dust.DUST_EINVAL
     assert L.dust_batch_create(*args, 9, ctypes.byref(n)) == dust.DUST_EINVAL  # bad flags
     assert L.dust_batch_form(None, None, None, None) == dust.DUST_EINVAL
+
+
+def test_batch_run_noalloc_limits(L):
+    """The no-allocation batched launch refuses, before any HIP call, more
+    grids or more tiles than its fixed work-list array holds."""
+    n = 257
+    nc = (ctypes.c_int64 * n)(*([16] * n))
+    z = (ctypes.c_void_p * n)()
+    ld = (ctypes.c_int64 * n)(*([8] * n))
+    v = lambda a: ctypes.cast(a, ctypes.c_void_p)
+    args = [v(z), n, v(nc), v(z), v(ld), v(z), v(z), v(ld), v(z), v(ld), None, None]
+    assert L.dust_batch_run_noalloc(*args) == dust.DUST_EINVAL
+    assert b"256 grids" in L.dust_last_error()
+    nc1 = (ctypes.c_int64 * 1)(16 * 600000)
+    args = [v(z), 1, v(nc1), v(z), v(ld), v(z), v(z), v(ld), v(z), v(ld), None, None]
+    assert L.dust_batch_run_noalloc(*args) == dust.DUST_EINVAL
+    assert b"tiles" in L.dust_last_error()
