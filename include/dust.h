@@ -115,6 +115,13 @@ typedef struct {
     double ltab_tmax;  /* highest tabulated T (K): mixed 3000, table-linear 1500 */
     int32_t f32_lookup; /* mixed: nonzero replaces the FP64 inverse-table
                            lookup by the FP32 one */
+    int32_t newton_polish; /* mixed (FP64 lookup): nonzero follows the lookup
+                           with an FP64 bracketed-Newton polish of Eq. 7 on the
+                           grain's forward table of ln P at the ltab_n
+                           temperatures (the cubic through the four table
+                           values around the bracketing interval); T is then
+                           the table's root to about 1e-11 before FP32
+                           rounding.  Not for batched launches. */
     int32_t reserved;  /* must be 0 */
 } dust_options;
 

@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", _i32), ("maxit", _i32), ("tol", ctypes.c_double),
                 ("ltab_n", _i32), ("fused_kernels", _i32),
                 ("ltab_tmin", ctypes.c_double), ("ltab_tmax", ctypes.c_double),
-                ("f32_lookup", _i32), ("reserved", _i32)]
+                ("f32_lookup", _i32), ("newton_polish", _i32), ("reserved", _i32)]
 
 
 class SolveExt(ctypes.Structure):
@@ -192,7 +192,7 @@ class Plan:
     """A grid's device tables (dust_plan)."""
 
     def __init__(self, grid, mode="plain", tol=0.0, maxit=0, ltab_n=0, ltab_tmin=0.0,
-                 ltab_tmax=0.0, fused_kernels=0, f32_lookup=False):
+                 ltab_tmax=0.0, fused_kernels=0, f32_lookup=False, newton_polish=False):
         self._keep = [np.ascontiguousarray(a, dtype=np.float64)
                       for a in (grid.lam, grid.dlam, grid.c_abs, grid.weight, grid.size)]
         lam, dlam, cabs, w, a = self._keep
@@ -202,7 +202,8 @@ class Plan:
         desc = GridDesc(self.n_lambda, self.n_grains, lam.ctypes.data, dlam.ctypes.data,
                         cabs.ctypes.data, w.ctypes.data, a.ctypes.data)
         opt = Options(self.mode, int(maxit), float(tol), int(ltab_n), int(fused_kernels),
-                      float(ltab_tmin), float(ltab_tmax), 1 if f32_lookup else 0, 0)
+                      float(ltab_tmin), float(ltab_tmax), 1 if f32_lookup else 0,
+                      1 if newton_polish else 0, 0)
         h = _vp()
         _check(lib().dust_plan_create(ctypes.byref(desc), ctypes.byref(opt), ctypes.byref(h)))
         self._h = h

@@ -82,6 +82,9 @@ dust_status resolve_options(const dust_options* in, dust_options* o) {
         return set_error(DUST_EINVAL, "fused_kernels must be 0, 1 or 2");
     if (d.reserved != 0) return set_error(DUST_EINVAL, "dust_options.reserved must be 0");
     d.f32_lookup = d.f32_lookup != 0;
+    d.newton_polish = d.newton_polish != 0;
+    if (d.newton_polish && (d.mode != DUST_MIXED || d.f32_lookup))
+        return set_error(DUST_EINVAL, "newton_polish needs DUST_MIXED with the FP64 lookup");
     if (d.ltab_tmin == 0.0) d.ltab_tmin = lin ? 3.0 : 2.7;
     if (d.ltab_tmax == 0.0) d.ltab_tmax = lin ? 1500.0 : 3000.0;
     if (!(d.ltab_tmin > 0.0) || !(d.ltab_tmax > d.ltab_tmin) || !isfinite(d.ltab_tmax) ||
@@ -309,6 +312,7 @@ dust_status dust_plan_create(const dust_grid_desc* g, const dust_options* opt, d
     v.ylof = p->d_ylof;
     v.dyinvf = p->d_dyinvf;
     v.f32_lookup = o.f32_lookup;
+    v.polish = o.newton_polish;
     v.tstep = tstep;
     v.q = nullptr;
     v.ldq = 0;

@@ -198,9 +198,10 @@ dust_status bind_grids(dust_plan* const* plans, int32_t n_grids, const int64_t* 
     for (int g = 0; g < n_grids; ++g) {
         const dust_plan* p = plans[g];
         if (!p) return set_error(DUST_EINVAL, "plans[" + std::to_string(g) + "] is NULL");
-        if (p->opt.mode != DUST_MIXED || p->opt.f32_lookup)
+        if (p->opt.mode != DUST_MIXED || p->opt.f32_lookup || p->opt.newton_polish)
             return set_error(DUST_EUNSUPPORTED,
-                             "batched launches take DUST_MIXED plans with the FP64 lookup");
+                             "batched launches take DUST_MIXED plans with the FP64 lookup "
+                             "(no FP32 lookup, no Newton polish)");
         if (n_cells[g] < 0 || n_cells[g] > ((int64_t)1 << 36))
             return set_error(DUST_EINVAL, "n_cells out of range");
         const int64_t c = n_cells[g];

@@ -455,12 +455,76 @@ __device__ __forceinline__ int table_lookup_f64(const PlanView& v, int s, float 
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Mixed solve with the FP64 Newton polish of Eq. 7 on the grain's forward
+// table (dust_options.newton_polish): the inverse-table lookup above gives
+// ln T0; the four forward-table values around the interval it falls in are
+// read at once, the interval whose powers bracket H' is taken among the
+// stencil's three (a step to a neighbour if rounding put ln T0 across a
+// node), and a Newton step in FP64 on y(ln T) = ln P'(T) -- the cubic through
+// the four values -- refines ln T inside that bracket (a step that would
+// leave it bisects it instead).  The start lies within about 1e-9 of the
+// cubic's root, so one step reaches FP64 rounding; what remains is the
+// cubic's own interpolation error (about 1e-11 in ln T at 4096 table points
+// over 2.7-3000 K).  Returns 0 with *T set, or nonzero for a pair outside the
+// table (solved exactly instead).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int table_lookup_polish(const PlanView& v, int s, float hs, float* T,
+                                                   dust_counters* cnt) {
+    if (!(hs >= 0.0f) || __builtin_isinf(hs)) {
+        if (cnt) count(&cnt->n_nonfinite);
+        *T = __builtin_nanf("");
+        return 0;
+    }
+    if (hs == 0.0f) { *T = 0.0f; return 0; }
+    if (hs < 1.17549435e-38f) return 1;  // subnormal
+    const double y = ln_normal_f32(hs);
+    const double u = (y - v.ylo[s]) * v.dyinv[s];
+    if (!(u >= 0.0 && u <= (double)(v.M - 1))) return 1;  // outside, or not finite
+    const int j = (int)u < v.M - 2 ? (int)u : v.M - 2;
+    const double2* g = v.invd + (int64_t)s * v.M + j;
+    const double2 g0 = g[0], g1 = g[1];
+    const double t = u - (double)j;
+    const double d = g1.x - g0.x;
+    const double c2 = 3.0 * d - 2.0 * g0.y - g1.y;
+    const double c3 = g0.y + g1.y - 2.0 * d;
+    const double lnT0 = g0.x + t * (g0.y + t * (c2 + t * c3));
+    // the stencil around the interval of ln T0, and the bracketing interval in it
+    const int N = v.N;
+    const double xk = (lnT0 - v.lnTmin) / v.hstep;
+    int k = (int)xk;
+    k = k < 0 ? 0 : (k > N - 2 ? N - 2 : k);
+    const int j0 = stencil_start(k, N);
+    const double* f = v.fwd + (int64_t)s * N + j0;
+    const double a0 = f[0], a1 = f[1], a2 = f[2], a3 = f[3];
+    int kk = k - j0;  // 0, 1 or 2
+    const double ylo_k = kk == 0 ? a0 : (kk == 1 ? a1 : a2);
+    const double yhi_k = kk == 0 ? a1 : (kk == 1 ? a2 : a3);
+    if (y < ylo_k && kk > 0) --kk;
+    else if (y > yhi_k && kk < 2) ++kk;
+    const double lo = (double)kk, hi = lo + 1.0;
+    double x = xk - (double)j0;
+    x = x < lo ? lo : (x > hi ? hi : x);
+    double dp;
+    const double r = cubic4(x, a0, a1, a2, a3, &dp) - y;
+    if (r != 0.0) {
+        const double xn = x - r / dp;
+        x = (xn >= lo && xn <= hi) ? xn : (r > 0.0 ? 0.5 * (lo + x) : 0.5 * (x + hi));
+    }
+    const double lnT = v.lnTmin + ((double)j0 + x) * v.hstep;
+    const float head = (float)lnT;
+    *T = expf(head) * (1.0f + (float)(lnT - (double)head));
+    return 0;
+}
+
 // The lookup of a mixed kernel form.
 template <int MODE>
 __device__ __forceinline__ int mixed_lookup(const PlanView& v, int s, float hs, float* T,
                                             dust_counters* cnt) {
     if constexpr (MODE == MODE_MIXED_F32) {
         return table_lookup_f32(v, s, hs, T, cnt);
+    } else if constexpr (MODE == MODE_MIXED_POLISH) {
+        return table_lookup_polish(v, s, hs, T, cnt);
     } else {
         return table_lookup_f64(v, s, hs, T, cnt);
     }

@@ -57,6 +57,9 @@ hipError_t launch_as_ntw(const PlanView& v, int64_t C, const float* J, int64_t l
     else if (km == MODE_MIXED_F32)
         hipLaunchKernelGGL((absorb_solve_kernel<MODE_MIXED_F32, NTW>), grid, dim3(256), lds,
                            st, v, C, J, ldj, T, ldt, cnt);
+    else if (km == MODE_MIXED_POLISH)
+        hipLaunchKernelGGL((absorb_solve_kernel<MODE_MIXED_POLISH, NTW>), grid, dim3(256), lds,
+                           st, v, C, J, ldj, T, ldt, cnt);
     else if (v.mode == DUST_TABLE_LINEAR)
         hipLaunchKernelGGL((absorb_solve_kernel<DUST_TABLE_LINEAR, NTW>), grid, dim3(256), lds,
                            st, v, C, J, ldj, T, ldt, cnt);
@@ -79,6 +82,9 @@ hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj,
     else if (km == MODE_MIXED_F32)
         hipLaunchKernelGGL((fused_kernel<MODE_MIXED_F32, NTW, TAIL>), grid, dim3(256), lds, st,
                            v, C, J, ldj, m, T, ldt, L, ldl, cnt);
+    else if (km == MODE_MIXED_POLISH)
+        hipLaunchKernelGGL((fused_kernel<MODE_MIXED_POLISH, NTW, TAIL>), grid, dim3(256), lds,
+                           st, v, C, J, ldj, m, T, ldt, L, ldl, cnt);
     else if (v.mode == DUST_TABLE_LINEAR)
         hipLaunchKernelGGL((fused_kernel<DUST_TABLE_LINEAR, NTW, TAIL>), grid, dim3(256), lds,
                            st, v, C, J, ldj, m, T, ldt, L, ldl, cnt);

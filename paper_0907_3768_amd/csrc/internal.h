@@ -63,6 +63,7 @@ struct PlanView {
     const float* ylof;     // [S] float(ylo)
     const float* dyinvf;   // [S] float(dyinv)
     int f32_lookup;        // mixed: FP32 inverse-table lookup instead of the FP64 one
+    int polish;            // mixed: FP64 Newton polish on the forward table after the lookup
     int N, M;
     double lnTmin, hstep;  // ln T_k = lnTmin + k hstep
     const double* texp;    // [N] T_k: exp(lnTmin + k hstep) (mixed),
@@ -159,13 +160,18 @@ hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ld
 // inverse-table lookup in place of the FP64 one (a separate instantiation,
 // so that it carries none of the FP64 code and registers).
 constexpr int MODE_MIXED_F32 = 3;
+// The default mixed lookup followed by the FP64 Newton polish on the forward
+// table (dust_options.newton_polish).
+constexpr int MODE_MIXED_POLISH = 4;
 // Forms whose heating runs on bf16 hi+lo MFMA and whose T comes from a table.
 __host__ __device__ constexpr bool table_mode(int mode) { return mode != DUST_PLAIN_FP32; }
 __host__ __device__ constexpr bool mixed_mode(int mode) {
-    return mode == DUST_MIXED || mode == MODE_MIXED_F32;
+    return mode == DUST_MIXED || mode == MODE_MIXED_F32 || mode == MODE_MIXED_POLISH;
 }
 inline int kernel_mode(const PlanView& v) {
-    return (v.mode == DUST_MIXED && v.f32_lookup) ? MODE_MIXED_F32 : v.mode;
+    if (v.mode == DUST_MIXED && v.f32_lookup) return MODE_MIXED_F32;
+    if (v.mode == DUST_MIXED && v.polish) return MODE_MIXED_POLISH;
+    return v.mode;
 }
 hipError_t launch_emit(const PlanView& v, int64_t C, const float* T, int64_t ldt,
                        const float* m, float* L, int64_t ldl, hipStream_t st);

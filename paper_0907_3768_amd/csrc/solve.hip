@@ -141,6 +141,10 @@ hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ld
             hipLaunchKernelGGL(solve_mixed_kernel<MODE_MIXED_F32>,
                                dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, C, H, ldh,
                                T, ldt, cnt);
+        else if (v.polish)
+            hipLaunchKernelGGL(solve_mixed_kernel<MODE_MIXED_POLISH>,
+                               dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, C, H, ldh,
+                               T, ldt, cnt);
         else
             hipLaunchKernelGGL(solve_mixed_kernel<DUST_MIXED>, dim3((unsigned)((n + 255) / 256)),
                                dim3(256), 0, st, v, C, H, ldh, T, ldt, cnt);

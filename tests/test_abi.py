@@ -70,13 +70,16 @@ def _desc(nl=8, s=2, lam=None, cabs=None, size=None):
     ("bad_trange", dust.DUST_EINVAL),
     ("bad_fused_kernels", dust.DUST_EINVAL),
     ("options_reserved", dust.DUST_EINVAL),
+    ("polish_plain", dust.DUST_EINVAL),
+    ("polish_f32_lookup", dust.DUST_EINVAL),
+    ("polish_table", dust.DUST_EINVAL),
 ])
 def test_plan_create_rejects(L, case, expect):
     nl, s = 8, 2
     lam = np.geomspace(1e-7, 1e-3, nl)
     cabs = np.full((s, nl), 1e-14)
     size = np.full(s, 1e-7)
-    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0, 0, 0)
+    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0, 0, 0, 0)
     if case == "nl0":
         nl = 0
     if case == "s0":
@@ -109,6 +112,12 @@ def test_plan_create_rejects(L, case, expect):
         opt.fused_kernels = 3
     if case == "options_reserved":
         opt.reserved = 1
+    if case == "polish_plain":           # the polish refines the mixed lookup only
+        opt.newton_polish = 1
+    if case == "polish_f32_lookup":
+        opt.mode, opt.f32_lookup, opt.newton_polish = dust.MIXED, 1, 1
+    if case == "polish_table":
+        opt.mode, opt.newton_polish = dust.TABLE_LINEAR, 1
     d, keep = _desc(max(nl, 1), max(s, 1), lam if nl else None, cabs if s else None,
                     size if s else None)
     d.n_lambda, d.n_grains = nl, s
@@ -121,7 +130,7 @@ def test_plan_create_rejects(L, case, expect):
 
 def test_null_arguments(L):
     d, keep = _desc()
-    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0, 0, 0)
+    opt = dust.Options(0, 0, 0.0, 0, 0, 0.0, 0.0, 0, 0, 0)
     assert L.dust_plan_create(None, ctypes.byref(opt), ctypes.byref(ctypes.c_void_p())) == dust.DUST_EINVAL
     assert L.dust_plan_create(ctypes.byref(d), ctypes.byref(opt), None) == dust.DUST_EINVAL
     d.lambda_ = None

@@ -64,7 +64,7 @@ def _run(plan, J, m, path, counters=None):
 
 # --------------------------------------------------------------------------- small, full compare
 
-@pytest.mark.parametrize("mode", ["plain", "mixed", "mixed-f32"])
+@pytest.mark.parametrize("mode", ["plain", "mixed", "mixed-f32", "mixed-polish"])
 @pytest.mark.parametrize("path", ["separate", "fused", "fused2"])
 def test_small_full_compare(dev, mode, path):
     w = synth.WORKLOADS["small-1024x120x20"]
@@ -72,8 +72,10 @@ def test_small_full_compare(dev, mode, path):
     say(f"small-1024x120x20 mode={mode} path={path}")
     J, m = _inputs(g, w.n_cells, w.seed, dev)
     f32 = mode == "mixed-f32"
-    mode = "mixed" if f32 else mode
-    plan = dust.Plan(g, mode, fused_kernels=2 if path == "fused2" else 1, f32_lookup=f32)
+    polish = mode == "mixed-polish"
+    mode = "mixed" if (f32 or polish) else mode
+    plan = dust.Plan(g, mode, fused_kernels=2 if path == "fused2" else 1, f32_lookup=f32,
+                     newton_polish=polish)
     path = "fused" if path == "fused2" else path
     cnt = dust.new_counters(dev)
     H, T, L = _run(plan, J, m, path, cnt)
@@ -171,21 +173,28 @@ def test_zero_field_and_nan(dev, mode):
                              Lh[keep])
 
 
-@pytest.mark.parametrize("f32,ltab_n,bound", [(False, 0, 3e-7), (True, 0, 4e-6),
-                                               (False, 4096, 3e-7)])
-def test_mixed_lookup_precision(dev, f32, ltab_n, bound):
+@pytest.mark.parametrize("f32,ltab_n,polish,bound", [(False, 0, False, 3e-7),
+                                                      (True, 0, False, 4e-6),
+                                                      (False, 4096, False, 3e-7),
+                                                      (False, 1024, True, 2.5e-7),
+                                                      (False, 4096, True, 2.5e-7)])
+def test_mixed_lookup_precision(dev, f32, ltab_n, polish, bound):
     """The mixed temperature step alone: given the oracle's FP64 heating
     rounded to FP32, T must match the oracle's root of Eq. 7 for exactly that
     H to the lookup's own error (FP64 inverse table: interpolation ~1e-9,
     plus FP32 rounding of T; FP32 lookup: FP32 rounding of ln H').  With the
-    default 1024 table temperatures and with 4096."""
+    default 1024 table temperatures and with 4096.  With the FP64 Newton
+    polish on the forward table (interpolation error about 1e-11) what
+    remains is the FP32 arithmetic of T = expf(head) (1 + tail): expf to
+    about 1 ulp, the product and the final rounding half an ulp each, at most
+    2 ulp = 2.4e-7 relative, and ln H' to about 4e-8 (a fifth of that in T)."""
     w = synth.WORKLOADS["small-1024x120x20"]
     g = w.grid()
     J, _ = _inputs(g, 512, 23, dev)
     H64 = oracle.heating(_host(J).astype(np.float64), g.c_abs, g.dlam)
     H32 = H64.astype(np.float32)
     T_ref = oracle.temperature(H32.astype(np.float64), g.lam, g.dlam, g.c_abs, g.size)
-    plan = dust.Plan(g, "mixed", f32_lookup=f32, ltab_n=ltab_n)
+    plan = dust.Plan(g, "mixed", f32_lookup=f32, ltab_n=ltab_n, newton_polish=polish)
     cnt = dust.new_counters(dev)
     T = plan.solve(torch.as_tensor(H32, device=dev), counters=cnt)
     torch.cuda.synchronize()
@@ -194,15 +203,15 @@ def test_mixed_lookup_precision(dev, f32, ltab_n, bound):
     assert err.max() <= bound
 
 
-@pytest.mark.parametrize("f32", [False, True])
-def test_cold_cells_use_exact_fallback(dev, f32):
+@pytest.mark.parametrize("f32,polish", [(False, False), (True, False), (False, True)])
+def test_cold_cells_use_exact_fallback(dev, f32, polish):
     """Pairs colder than the table's 2.7 K take the exact FP64 solve."""
     g = synth.make_grid(120, 2, 10)
     p = synth.cell_params(32, 17)
     p.logw[:, :] = -22.0  # very weak fields: T well below 2.7 K for big grains
     J = synth.radiation_field(p, g.lam, device=dev)
     m = torch.ones(32, dtype=torch.float32, device=dev)
-    plan = dust.Plan(g, "mixed", f32_lookup=f32)
+    plan = dust.Plan(g, "mixed", f32_lookup=f32, newton_polish=polish)
     cnt = dust.new_counters(dev)
     T, L = plan.fused(J, m, counters=cnt)
     torch.cuda.synchronize()
@@ -211,7 +220,7 @@ def test_cold_cells_use_exact_fallback(dev, f32):
     check_against_oracle(g, _host(J), np.ones(32), _host(T), _host(L))
 
 
-@pytest.mark.parametrize("mode", ["plain", "mixed", "mixed-f32"])
+@pytest.mark.parametrize("mode", ["plain", "mixed", "mixed-f32", "mixed-polish"])
 def test_hot_cells_above_table(dev, mode):
     """Fields strong enough to heat grains above the table's 3000 K: the mixed
     path solves them exactly, the plain path by Newton as everywhere."""
@@ -221,7 +230,9 @@ def test_hot_cells_above_table(dev, mode):
     J = synth.radiation_field(p, g.lam, device=dev)
     m = torch.ones(32, dtype=torch.float32, device=dev)
     f32 = mode == "mixed-f32"
-    plan = dust.Plan(g, "mixed" if f32 else mode, f32_lookup=f32)
+    polish = mode == "mixed-polish"
+    plan = dust.Plan(g, "mixed" if (f32 or polish) else mode, f32_lookup=f32,
+                     newton_polish=polish)
     cnt = dust.new_counters(dev)
     T, L = plan.fused(J, m, counters=cnt)
     torch.cuda.synchronize()
@@ -392,20 +403,26 @@ def test_deterministic_and_prepare(dev, mode):
 # (workload, mode, table temperatures of the mixed form; 0 = the default 1024).
 # The million-cell workload also runs with the 4096 log-spaced table
 # temperatures its configuration states.
-FULL = [("plain-262144x250x80", "plain", 0), ("plain-262144x250x80", "mixed", 0),
-        ("mixed-1048576x500x128", "mixed", 0), ("mixed-1048576x500x128", "mixed", 4096),
-        ("full-4194304x1000x240", "mixed", 0)]
+# (workload, mode, table temperatures of the mixed form (0 = the default
+# 1024), FP64 Newton polish).  The million-cell workload also runs as its
+# configuration states it: 4096 log-spaced table temperatures and the polish;
+# the 4M-cell workload also with the polish its configuration states.
+FULL = [("plain-262144x250x80", "plain", 0, False), ("plain-262144x250x80", "mixed", 0, False),
+        ("mixed-1048576x500x128", "mixed", 0, False),
+        ("mixed-1048576x500x128", "mixed", 4096, True),
+        ("full-4194304x1000x240", "mixed", 0, False),
+        ("full-4194304x1000x240", "mixed", 0, True)]
 
 
-@pytest.mark.parametrize("name,mode,ltab_n", FULL)
-def test_full_size_sampled(dev, name, mode, ltab_n):
+@pytest.mark.parametrize("name,mode,ltab_n,polish", FULL)
+def test_full_size_sampled(dev, name, mode, ltab_n, polish):
     w = synth.WORKLOADS[name]
     g = w.grid()
-    say(f"full size {name} mode={mode} ltab_n={ltab_n}: generating J")
+    say(f"full size {name} mode={mode} ltab_n={ltab_n} polish={polish}: generating J")
     p = w.cells()
     J = synth.radiation_field(p, g.lam, device=dev)
     m = torch.as_tensor(p.m_dust, dtype=torch.float32, device=dev)
-    plan = dust.Plan(g, mode, ltab_n=ltab_n)
+    plan = dust.Plan(g, mode, ltab_n=ltab_n, newton_polish=polish)
     cnt = dust.new_counters(dev)
     say(f"full size {name} mode={mode}: running")
     if mode == "plain":
