@@ -7,7 +7,10 @@ no code, header, table or constant with the GPU path.
 The arithmetic lives in ``dust_ref.c`` (plain C, IEEE double precision, one
 function per equation of Section 4: Eq. 6 heating, Eq. 7 temperature root,
 Eqs. 9-10 emission, Eq. 11 initial guess, and the production variant of the
-temperature step: linear interpolation in a table of the grain power).  This
+temperature step: linear interpolation in a table of the grain power) and
+``fluct_ref.c`` (thermally fluctuating grains, Sections 2 and 6: the level
+distribution under single-photon heating and continuous cooling, and the
+emission averaged over it).  This
 module builds that file with gcc, marshals numpy arrays to it, and adds the
 non-radiative heating term and the outer re-heating iteration (Section 2) as
 plain numpy around those calls.
@@ -30,6 +33,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dust_ref.c")
+_SRC_FLUCT = os.path.join(_HERE, "fluct_ref.c")
 _LIB_PATH = os.path.join(_HERE, "libdust_ref.so")
 _lib = None
 
@@ -45,7 +49,7 @@ def build(force: bool = True) -> str:
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+           "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, _SRC_FLUCT, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -75,6 +79,14 @@ def lib():
         L.dust_ref_table_build.argtypes = [_i32, _i32, _p, _p, _p, _i32, _d, _d, _p]
         L.dust_ref_table_temperature.restype = _i64
         L.dust_ref_table_temperature.argtypes = [_i64, _i32, _i32, _d, _d, _p, _p, _p]
+        L.dust_ref_fluct_pair.restype = None
+        L.dust_ref_fluct_pair.argtypes = [_i32, _i32, _p, _p, _p, _p, _p, _p, _p]
+        L.dust_ref_fluct_distribution.restype = None
+        L.dust_ref_fluct_distribution.argtypes = [_i64, _i32, _i32, _i32, _p, _p, _p, _p, _p,
+                                                  _p, _i64, _p]
+        L.dust_ref_fluct_emission.restype = None
+        L.dust_ref_fluct_emission.argtypes = [_i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p,
+                                              _p]
         L.dust_ref_get_threads.restype = ctypes.c_int
         L.dust_ref_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -212,6 +224,36 @@ def reheat(grid, J0, m_dust, coupling, n_passes, Q=None, table=None):
         out.append((H, T, L))
         J = J0 + g * L
     return out
+
+
+def fluct_distribution(J, grid, lev_T, lev_E):
+    """Thermally fluctuating grains: P[C, S, M], the steady-state probability
+    of each of a grain's M enthalpy levels (lev_E [S, M], J; at temperatures
+    lev_T [S, M], K; level 0 the ground state E = T = 0) under single-photon
+    heating by the field J[C, NL] and continuous cooling (see fluct_ref.c)."""
+    J = _f64(J)
+    lam, dlam, c_abs = _f64(grid.lam), _f64(grid.dlam), _f64(grid.c_abs)
+    lev_T, lev_E = _f64(lev_T), _f64(lev_E)
+    C, NL = J.shape
+    S, M = lev_T.shape
+    assert c_abs.shape == (S, NL) and lev_E.shape == (S, M) and M >= 2
+    P = np.empty((C, S, M), dtype=np.float64)
+    lib().dust_ref_fluct_distribution(C, NL, S, M, _ptr(lam), _ptr(dlam), _ptr(c_abs),
+                                      _ptr(lev_T), _ptr(lev_E), _ptr(J), NL, _ptr(P))
+    return P
+
+
+def fluct_emission(P, grid, lev_T, m_dust=None):
+    """L[C, NL] = m[c] sum_s w_s C[s,l] sum_j P[c,s,j] B(lam_l, T_sj)."""
+    P = _f64(P)
+    lam, c_abs, weight, lev_T = _f64(grid.lam), _f64(grid.c_abs), _f64(grid.weight), _f64(lev_T)
+    C, S, M = P.shape
+    NL = lam.shape[0]
+    md = _f64(m_dust) if m_dust is not None else None
+    L = np.empty((C, NL), dtype=np.float64)
+    lib().dust_ref_fluct_emission(C, NL, S, M, _ptr(lam), _ptr(c_abs), _ptr(weight),
+                                  _ptr(lev_T), _ptr(md), _ptr(P), _ptr(L))
+    return L
 
 
 def threads() -> int:

@@ -84,6 +84,30 @@ int64_t dust_ref_table_temperature(int64_t n_cells, int32_t S, int32_t n_T,
                                    double t_min, double t_max, const double* P,
                                    const double* H, double* T);
 
+/* Thermally fluctuating grains (fluct_ref.c): the steady-state probability
+ * distribution over a grain's M >= 2 enthalpy levels (E_0 = 0 < E_1 < ...,
+ * temperatures T_0 = 0 < T_1 < ...) under single-photon heating and
+ * continuous cooling, and the emission averaged over it.
+ * One pair: J[NL] of the cell, c_row[NL] of the grain, lev_T/lev_E[M] of the
+ * grain; P[M] receives the distribution (NaN when J holds a negative or
+ * non-finite value). */
+void dust_ref_fluct_pair(int32_t NL, int32_t M, const double* lam, const double* dlam,
+                         const double* c_row, const double* lev_T, const double* lev_E,
+                         const double* J, double* P);
+
+/* Every pair: lev_T/lev_E [S][M], J[c*ldj + l], P[(c*S + s)*M + j]. */
+void dust_ref_fluct_distribution(int64_t n_cells, int32_t NL, int32_t S, int32_t M,
+                                 const double* lam, const double* dlam, const double* c_abs,
+                                 const double* lev_T, const double* lev_E, const double* J,
+                                 int64_t ldj, double* P);
+
+/* L[c*NL + l] = m[c] sum_s w_s C[s,l] sum_j P[c,s,j] B(lam_l, T_sj); m_dust
+ * may be NULL. */
+void dust_ref_fluct_emission(int64_t n_cells, int32_t NL, int32_t S, int32_t M,
+                             const double* lam, const double* c_abs, const double* weight,
+                             const double* lev_T, const double* m_dust, const double* P,
+                             double* L);
+
 /* OpenMP thread control (the oracle parallelises over cells only). */
 int dust_ref_get_threads(void);
 void dust_ref_set_threads(int n);

@@ -278,3 +278,98 @@ def reheat_coupling(grid: Grid, m_dust: np.ndarray, seed: int) -> np.ndarray:
     f = rng.uniform(0.1, 0.5, size=m_dust.shape[0])
     kappa_max = float((grid.weight[:, None] * grid.c_abs).sum(axis=0).max())
     return f / (np.asarray(m_dust, dtype=np.float64) * kappa_max)
+
+
+# ---------------------------------------------------------------------------
+# Thermally fluctuating grains: enthalpy levels from a heat-capacity model.
+#
+# The paper's discussion of fluctuating grains needs each grain's heat
+# capacity, which is not among its inputs.  Stand-in: a three-dimensional
+# Debye solid of carbon atoms (graphite-like density 2240 kg m^-3, 12 u per
+# atom) with Debye temperature 420 K; a grain of radius a holds
+# N = (4 pi / 3) a^3 rho / m_atom atoms and its enthalpy above the ground
+# state at temperature T is
+#   E(T) = 9 N k T (T / theta)^3 int_0^{theta/T} x^3 / (e^x - 1) dx.
+# Levels: E_0 = 0 at T_0 = 0, then temperatures log-spaced over
+# [t_lo, t_hi] and their enthalpies.
+# ---------------------------------------------------------------------------
+
+DEBYE_THETA_K = 420.0
+GRAIN_DENSITY = 2240.0                     # kg m^-3
+ATOM_MASS = 12.0 * 1.66053906660e-27       # kg
+
+
+def grain_atoms(a_m):
+    """Atoms in a grain of radius a (m) of the Debye stand-in."""
+    return 4.0 / 3.0 * math.pi * np.asarray(a_m, dtype=np.float64) ** 3 * GRAIN_DENSITY / ATOM_MASS
+
+
+def debye_enthalpy(T, n_atoms, theta=DEBYE_THETA_K):
+    """E(T) of the Debye stand-in (J) for temperatures T (K) >= 0."""
+    from scipy.integrate import quad
+    T = np.asarray(T, dtype=np.float64)
+    out = np.zeros_like(T)
+    for idx, t in np.ndenumerate(T):
+        if t <= 0.0:
+            continue
+        y = theta / t
+        val, _ = quad(lambda x: x ** 3 / math.expm1(x) if x > 0 else 0.0, 0.0, y,
+                      epsabs=0.0, epsrel=1e-13, limit=200)
+        out[idx] = 9.0 * n_atoms * _K * t * (t / theta) ** 3 * val
+    return out
+
+
+def fluct_levels(grid: Grid, n_levels: int = 64, t_lo: float = 2.0, t_hi: float = 2500.0):
+    """Level temperatures and enthalpies [S, n_levels] of every grain of the
+    grid: level 0 the ground state (T = 0, E = 0), levels 1 .. n - 1 at
+    temperatures log-spaced over [t_lo, t_hi]."""
+    S = grid.n_grains
+    T1 = np.concatenate([[0.0], np.geomspace(t_lo, t_hi, n_levels - 1)])
+    lev_T = np.repeat(T1[None, :], S, axis=0)
+    lev_E = np.empty_like(lev_T)
+    for s in range(S):
+        lev_E[s] = debye_enthalpy(T1, float(grain_atoms(grid.size[s])))
+    return lev_T, lev_E
+
+
+def make_species_grid(n_lambda: int, species: Sequence[int], n_sizes: int,
+                      lo_um: float = 0.09, hi_um: float = 1000.0) -> Grid:
+    """A grid with the listed species (0-based indices), n_sizes sizes each."""
+    lam, dlam = wavelength_grid(n_lambda, lo_um, hi_um)
+    cs, ws, as_, sp = [], [], [], []
+    for i in species:
+        beta, kappa, amin, amax = SPECIES[i]
+        c, w, a = species_grains(lam, beta, kappa, amin, amax, n_sizes)
+        cs.append(c)
+        ws.append(w)
+        as_.append(a)
+        sp.append(np.full(n_sizes, i, dtype=np.int32))
+    return Grid(lam, dlam, np.concatenate(cs), np.concatenate(ws), np.concatenate(as_),
+                np.concatenate(sp))
+
+
+@dataclasses.dataclass
+class FluctWorkload:
+    """Fluctuating very small grains: species 3 (0.35-10 nm), n_sizes sizes,
+    n_levels enthalpy levels from the Debye stand-in over 2-2500 K."""
+    name: str
+    n_cells: int
+    n_lambda: int
+    n_sizes: int
+    n_levels: int
+    seed: int
+
+    def grid(self) -> Grid:
+        return make_species_grid(self.n_lambda, [2], self.n_sizes)
+
+    def levels(self, grid: Grid):
+        return fluct_levels(grid, self.n_levels)
+
+    def cells(self) -> CellParams:
+        return cell_params(self.n_cells, self.seed)
+
+
+FLUCT_WORKLOADS = {
+    # 65536 cells x 250 wavelengths x 16 very small grains x 64 levels
+    "fluct-65536x250x16x64": FluctWorkload("fluct-65536x250x16x64", 65536, 250, 16, 64, 5),
+}
