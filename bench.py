@@ -83,6 +83,16 @@ def measured_traffic(kernel_key, src_hash):
     return e.get("bytes_per_launch")
 
 
+def host_rows(t, rows):
+    """Rows `rows` of a device tensor as a host numpy array, after checking
+    on the host that every index lies inside the tensor."""
+    import torch
+    rows = np.asarray(rows, dtype=np.int64)
+    if rows.size and not (0 <= int(rows.min()) and int(rows.max()) < t.shape[0]):
+        raise IndexError(f"row {int(rows.max())} outside a tensor of {t.shape[0]} rows")
+    return t[torch.as_tensor(rows, device=t.device)].cpu().numpy()
+
+
 def committed_json(name):
     try:
         with open(os.path.join(ROOT, "profiles", name)) as f:
@@ -181,12 +191,10 @@ def check_sample(grid, J, m_host, T, L, n_sample=64, table=None):
     from oracle.compare import sed_errors, t_errors
     C = J.shape[0]
     rows = np.arange(min(n_sample, C)) * max(1, C // n_sample)
-    import torch
-    idx = torch.as_tensor(rows, device=J.device)
-    Jh = J[idx].cpu().numpy().astype(np.float64)
+    Jh = host_rows(J, rows).astype(np.float64)
     H_ref, T_ref, L_ref = oracle.run(grid, Jh, m_host[rows], table=table)
-    te = t_errors(T[idx].cpu().numpy(), T_ref, H_ref)
-    se = sed_errors(L[idx].cpu().numpy(), L_ref, grid.dlam)
+    te = t_errors(host_rows(T, rows), T_ref, H_ref)
+    se = sed_errors(host_rows(L, rows), L_ref, grid.dlam)
     return {"cells": int(len(rows)), "T_max_rel": te["max"], "T_p999_rel": te["p999"],
             "SED_max_rel": se["max"], "SED_energy_l1": se["energy_l1"],
             "SED_weighted_ratio_dev": se["weighted_ratio_dev"]}
@@ -202,7 +210,7 @@ def cpu_baseline(grid, J, m_host, target_s, n_cells=None):
 
     def run(n):
         rows = np.arange(n) * max(1, C // n)
-        Jh = J[torch.as_tensor(rows, device=J.device)].cpu().numpy().astype(np.float64)
+        Jh = host_rows(J, rows).astype(np.float64)
         t0 = time.perf_counter()
         oracle.run(grid, Jh, m_host[rows])
         return time.perf_counter() - t0
@@ -292,13 +300,12 @@ def run_reheat_leg(torch, synth, dust, grid, params, J0, m, T, L, cnt, n_passes=
                      "j_update_ms_per_pass": [t[0] for t in times]}
         if name == "plain_warm":
             rows = np.arange(32) * max(1, C // 32)
-            idx = torch.as_tensor(rows, device=J0.device)
-            passes = oracle.reheat(grid, J0[idx].cpu().numpy().astype(np.float64),
+            passes = oracle.reheat(grid, host_rows(J0, rows).astype(np.float64),
                                    params.m_dust[rows].astype(np.float32).astype(np.float64),
                                    coupling[rows].astype(np.float64), n_passes)
             H_ref, T_ref, L_ref = passes[-1]
-            te = t_errors(T[idx].cpu().numpy(), T_ref, H_ref)
-            se = sed_errors(L[idx].cpu().numpy(), L_ref, grid.dlam)
+            te = t_errors(host_rows(T, rows), T_ref, H_ref)
+            se = sed_errors(host_rows(L, rows), L_ref, grid.dlam)
             out["errors_last_pass_vs_oracle"] = {"cells": 32, "T_max_rel": te["max"],
                                                  "SED_max_rel": se["max"]}
     w, c = out["plain_warm"], out["plain_cold"]
@@ -374,11 +381,10 @@ def run_batch(args, torch, synth, dust, dev):
         worst = {"T_max_rel": 0.0, "SED_max_rel": 0.0, "SED_energy_l1": 0.0}
         for g, p, J, T, L in zip(grids, params, Js, Ts, Ls):
             rows = np.arange(min(n_per_grid, J.shape[0])) * max(1, J.shape[0] // n_per_grid)
-            idx = torch.as_tensor(rows, device=dev)
-            H_ref, T_ref, L_ref = oracle.run(g, J[idx].cpu().numpy().astype(np.float64),
+            H_ref, T_ref, L_ref = oracle.run(g, host_rows(J, rows).astype(np.float64),
                                              p.m_dust[rows])
-            te = t_errors(T[idx].cpu().numpy(), T_ref, H_ref)
-            se = sed_errors(L[idx].cpu().numpy(), L_ref, g.dlam)
+            te = t_errors(host_rows(T, rows), T_ref, H_ref)
+            se = sed_errors(host_rows(L, rows), L_ref, g.dlam)
             worst["T_max_rel"] = max(worst["T_max_rel"], te["max"])
             worst["SED_max_rel"] = max(worst["SED_max_rel"], se["max"])
             worst["SED_energy_l1"] = max(worst["SED_energy_l1"], se["energy_l1"])
@@ -433,7 +439,7 @@ def run_batch(args, torch, synth, dust, dev):
         while True:
             for g, p, J in zip(grids, params, Js):
                 rows = np.arange(per) * max(1, J.shape[0] // per)
-                Jh = J[torch.as_tensor(rows, device=dev)].cpu().numpy().astype(np.float64)
+                Jh = host_rows(J, rows).astype(np.float64)
                 ts = time.perf_counter()
                 oracle.run(g, Jh, p.m_dust[rows])
                 n_done += per * g.n_grains
@@ -449,6 +455,83 @@ def run_batch(args, torch, synth, dust, dev):
     out["accuracy_ok"] = bool(ok)
     print(json.dumps(out), flush=True)
     return 0 if ok else 3
+
+
+FP64_VECTOR_PEAK = 78.6e12   # MI355X FP64 vector FLOP/s
+FP32_MFMA_PEAK = 157.3e12    # MI355X dense FP32 MFMA FLOP/s
+FLUCT_WORKLOAD = "fluct-65536x250x16x64"
+
+
+def run_fluct_leg(torch, synth, dust, dev, steps, warmup, cpu_seconds=None):
+    """Thermally fluctuating grains on their workload (65536 cells x 250
+    wavelengths x 16 very small grains x 64 enthalpy levels): the level
+    distributions (dust_fluct_solve_P) and the emission averaged over them
+    (dust_fluct_emit_sed), timed with HIP events, checked against the oracle
+    on strided cells, each kernel against its own roofline."""
+    import oracle
+    w = synth.FLUCT_WORKLOADS[FLUCT_WORKLOAD]
+    g = w.grid()
+    lev_T, lev_E = w.levels(g)
+    params = w.cells()
+    C, NL, S, M = w.n_cells, g.n_lambda, g.n_grains, w.n_levels
+    J = synth.radiation_field(params, g.lam, device=dev)
+    m = torch.as_tensor(params.m_dust, dtype=torch.float32, device=dev)
+    P = torch.empty((C, S * M), dtype=torch.float32, device=dev)
+    L = torch.empty((C, NL), dtype=torch.float32, device=dev)
+    cnt = dust.new_counters(dev)
+    plan = dust.FluctPlan(g, lev_T, lev_E)
+    stages = [("solve_P", lambda: plan.solve_P(J, P, counters=cnt)),
+              ("emit", lambda: plan.emit(P, m, L))]
+    ms, k = time_steps(torch, stages, steps, warmup)
+    torch.cuda.synchronize()
+    rows = np.arange(16) * (C // 16)
+    Jh = host_rows(J, rows).astype(np.float64)
+    P_ref = oracle.fluct_distribution(Jh, g, lev_T, lev_E)
+    Pg = host_rows(P, rows).reshape(len(rows), S, M).astype(np.float64)
+    big = P_ref >= 1e-30
+    from oracle.compare import sed_errors
+    L_ref = oracle.fluct_emission(P_ref, g, lev_T, params.m_dust[rows])
+    se = sed_errors(host_rows(L, rows), L_ref, g.dlam)
+    pairs = C * S
+    flops_solve = pairs * (8.0 * M * (M - 1) / 2 + 4.0 * NL)
+    flops_emit = 2.0 * C * S * M * NL
+    out = {"workload": FLUCT_WORKLOAD, "cells": C, "n_lambda": NL, "n_grains": S, "levels": M,
+           "metric": "(cell,grain) level distributions/s incl. the averaged SED",
+           "value": pairs / (ms * 1e-3), "ms_per_step": ms, "stages_ms": k, "steps": steps,
+           "roofline": {
+               "solve_P": {"bound": "alu", "unit": "TFLOP/s (FP64 vector)",
+                           "algorithmic_flops": flops_solve,
+                           "achieved": flops_solve / (k["solve_P"] * 1e-3) / 1e12,
+                           "peak": FP64_VECTOR_PEAK / 1e12,
+                           "frac": flops_solve / (k["solve_P"] * 1e-3) / FP64_VECTOR_PEAK},
+               "emit": {"bound": "mfma", "unit": "TFLOP/s (FP32 MFMA)",
+                        "algorithmic_flops": flops_emit,
+                        "achieved": flops_emit / (k["emit"] * 1e-3) / 1e12,
+                        "peak": FP32_MFMA_PEAK / 1e12,
+                        "frac": flops_emit / (k["emit"] * 1e-3) / FP32_MFMA_PEAK}},
+           "errors": {"cells": len(rows),
+                      "P_max_rel": float((np.abs(Pg[big] - P_ref[big]) / P_ref[big]).max()),
+                      "SED_max_rel": se["max"], "SED_energy_l1": se["energy_l1"]},
+           "counters": dict(zip(COUNTER_NAMES, cnt.cpu().tolist()))}
+    if cpu_seconds:
+        # up to 1024 strided cells, 8 at a time, until the time is spent
+        n_max, stride = min(C, 1024), max(1, C // 1024)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < cpu_seconds and n < n_max:
+            r = np.arange(n, min(n + 8, n_max)) * stride
+            Jc = host_rows(J, r).astype(np.float64)
+            Pc = oracle.fluct_distribution(Jc, g, lev_T, lev_E)
+            oracle.fluct_emission(Pc, g, lev_T, params.m_dust[r])
+            n += len(r)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * S / dt, "unit": "(cell,grain) level distributions/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"{n} strided cells ({n * S} pairs, FP64 oracle incl. "
+                                         f"the averaged SED), {dt:.1f} s"}
+    out["accuracy_ok"] = bool(out["errors"]["P_max_rel"] <= 1e-6 and se["max"] <= 1e-3)
+    del plan, J, P, L
+    return out
 
 
 PROBE_KINDS = (("exp2", 0), ("rcp", 1), ("fma", 2), ("exp2+fma", 3), ("term", 4))
@@ -515,8 +598,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
                     help="full-4194304x1000x240 (default: the largest single-GPU workload), "
-                         "small-1024x120x20, plain-262144x250x80, mixed-1048576x500x128 or "
-                         "batch-64grids")
+                         "small-1024x120x20, plain-262144x250x80, mixed-1048576x500x128, "
+                         "batch-64grids or fluct-65536x250x16x64 (fluctuating grains)")
     ap.add_argument("--secondary-steps", type=int, default=5,
                     help="timed steps of each secondary form (at most --steps; one warm-up)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -565,6 +648,25 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batch-64grids":
         return run_batch(args, torch, synth, dust, dev)
+    if args.workload == FLUCT_WORKLOAD:
+        f = run_fluct_leg(torch, synth, dust, dev, args.steps, args.warmup,
+                          None if args.no_cpu_baseline else args.cpu_seconds)
+        out = {"metric": f["metric"], "value": f["value"], "unit": "(cell,grain) pairs/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+               "config": {"workload": FLUCT_WORKLOAD, "cells": f["cells"],
+                          "n_lambda": f["n_lambda"], "n_grains": f["n_grains"],
+                          "levels": f["levels"], "parallelism": "single GPU"},
+               "roofline": dict(f["roofline"]["solve_P"], kernel="fluct solve_kernel<1>",
+                                traffic=None),
+               "emit_roofline": f["roofline"]["emit"], "stages_ms": f["stages_ms"],
+               "errors": f["errors"], "counters": f["counters"],
+               "accuracy_ok": f["accuracy_ok"]}
+        if "cpu_baseline" in f:
+            out["cpu_baseline"] = f["cpu_baseline"]
+        print(json.dumps(out), flush=True)
+        return 0 if f["accuracy_ok"] else 3
     w = synth.WORKLOADS[args.workload]
     grid = w.grid()
     params = w.cells()
@@ -748,6 +850,9 @@ def main():
     log("timing re-heating passes")
     reheat_leg = run_reheat_leg(torch, synth, dust, grid, params, J, m, T, L, cnt)
 
+    log("timing thermally fluctuating grains (their own workload)")
+    fluct_leg = run_fluct_leg(torch, synth, dust, dev, k2, w2)
+
     plain_value = pairs / (plain_ms * 1e-3)
     out.update({
         "plain_fp32": {"value": plain_value, "ms_per_step": plain_ms, "stages_ms": plain_k,
@@ -780,6 +885,7 @@ def main():
                                      "value": pairs / (q_ms * 1e-3)},
         "table_linear": table_leg,
         "reheat_passes": reheat_leg,
+        "fluctuating_grains": fluct_leg,
         "mixed_over_plain": value / plain_value,
     })
     if not args.no_cpu_baseline:
@@ -793,7 +899,8 @@ def main():
           tpar["T_max_rel"] <= 1e-4 and tpar["SED_max_rel"] <= 1e-3 and
           all(x["errors"]["T_max_rel"] <= 1e-4 and x["errors"]["SED_max_rel"] <= 1e-3
               for x in polish_legs.values()) and
-          rerr["T_max_rel"] <= 1e-4 and rerr["SED_max_rel"] <= 1e-3)
+          rerr["T_max_rel"] <= 1e-4 and rerr["SED_max_rel"] <= 1e-3 and
+          fluct_leg["accuracy_ok"])
     out["accuracy_ok"] = bool(ok)
     print(json.dumps(out), flush=True)
     return 0 if ok else 3

@@ -304,6 +304,70 @@ dust_status dust_batch_run_noalloc(dust_plan* const* plans, int32_t n_grids,
                                    float* const* L, const int64_t* ldl,
                                    dust_counters* counters, void* stream);
 
+/* --- Thermally fluctuating grains ----------------------------------------
+ * Grains too small to hold the equilibrium temperature of Eq. 7 are heated
+ * in spikes by single photons and cool in between (Section 2; Section 6
+ * names the calculation and the transition-matrix method it takes).  For
+ * each cell and grain the library computes the steady-state probability of
+ * each of the grain's enthalpy levels, and the emission averaged over it:
+ *
+ *   levels    E_0 = 0 < E_1 < ... < E_{M-1} (J) at temperatures
+ *             T_0 = 0 < T_1 < ... (K), per grain (they follow from the grain's
+ *             heat capacity, which the caller supplies this way);
+ *   heating   photons of wavelength bin l (energy h c / lam_l, rate
+ *             J_l C_l dlam_l / (h c / lam_l)) lift the grain from level i to
+ *             E_i + h c / lam_l, shared between the two levels around it so
+ *             that the mean energy gained is the photon's (above the top
+ *             level: to the top level);
+ *   cooling   from level j > 0 to j - 1 at the rate P(T_j) / (E_j - E_{j-1}),
+ *             P(T) the grain power of Eq. 7;
+ *   P[c,s,j]  the steady state of those transitions, normalised to sum 1
+ *             (the flux balance across each level boundary, solved level by
+ *             level upwards in FP64);
+ *   L[c,l]    m[c] sum_s w_s C[s,l] sum_j P[c,s,j] B(lam_l, T_sj) (Eq. 10
+ *             averaged over the distribution).
+ * The common factor 4 pi of heating and cooling is dropped, as in Eq. 7. */
+typedef struct {
+    int32_t n_levels;     /* M, in [2, 256] */
+    const double* T;      /* [S][M] level temperatures (K): T[s][0] = 0, then
+                             strictly increasing, finite */
+    const double* E;      /* [S][M] level enthalpies (J): E[s][0] = 0, then
+                             strictly increasing, finite */
+} dust_levels;
+
+/* Opaque, library-owned plan of a grid's fluctuating grains. */
+typedef struct dust_fluct_plan dust_fluct_plan;
+
+/* Build the plan on the current device: upload the grid and the levels
+ * (host float64, read during the call only) and derive, on the device, the
+ * photon-rate weights, the cooling rates, the photon-count table of every
+ * level pair and the emission table; wait for them.  Allocates device
+ * memory.  DUST_EINVAL for a bad grid or levels, or when a level above the
+ * ground level radiates no power in FP64 (its temperature is too low for the
+ * wavelength grid). */
+dust_status dust_fluct_plan_create(const dust_grid_desc* grid, const dust_levels* levels,
+                                   dust_fluct_plan** out);
+
+/* Free a plan (waits for the device).  NULL is accepted. */
+dust_status dust_fluct_plan_destroy(dust_fluct_plan* plan);
+
+/* The level distributions: P[c*ldp + s*M + j] (float32, ldp >= S*M) from
+ * J[c*ldj + l].  A cell whose J holds a negative or non-finite value gets
+ * NaN for every level of every grain (counted in n_nonfinite per pair); a
+ * cell without radiation stays in the ground level.  Pairs that put more
+ * than 1e-6 of their probability on the top level (the levels end too low
+ * for the field) are counted in n_out_of_table.  counters may be NULL. */
+dust_status dust_fluct_solve_P(dust_fluct_plan* plan, int64_t n_cells,
+                               const float* J, int64_t ldj, float* P, int64_t ldp,
+                               dust_counters* counters, void* stream);
+
+/* The emission averaged over the distributions, L[c*ldl + l] (float32);
+ * m_dust may be NULL (unit mass).  accumulate nonzero adds to L instead of
+ * overwriting it (e.g. onto the equilibrium grains' SED of dust_run_fused). */
+dust_status dust_fluct_emit_sed(dust_fluct_plan* plan, int64_t n_cells,
+                                const float* P, int64_t ldp, const float* m_dust,
+                                float* L, int64_t ldl, int32_t accumulate, void* stream);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* dust_last_error(void);
 

@@ -46,6 +46,10 @@ class Options(ctypes.Structure):
                 ("f32_lookup", _i32), ("newton_polish", _i32), ("reserved", _i32)]
 
 
+class Levels(ctypes.Structure):
+    _fields_ = [("n_levels", _i32), ("T", _vp), ("E", _vp)]
+
+
 class SolveExt(ctypes.Structure):
     _fields_ = [("Q", _vp), ("ldq", _i64), ("warm_start", _i32), ("reserved", _i32)]
 
@@ -97,6 +101,11 @@ def lib():
         "dust_batch_run": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
         "dust_batch_run_noalloc": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    _vp],
+        "dust_fluct_plan_create": [ctypes.POINTER(GridDesc), ctypes.POINTER(Levels),
+                                   ctypes.POINTER(_vp)],
+        "dust_fluct_plan_destroy": [_vp],
+        "dust_fluct_solve_P": [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp],
+        "dust_fluct_emit_sed": [_vp, _i64, _vp, _i64, _vp, _vp, _i64, _i32, _vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -297,6 +306,71 @@ class Plan:
         T = self.solve(H, T=T, counters=counters, stream=stream, Q=Q, warm_start=warm_start)
         L = self.emit(T, m_dust, stream=stream)
         return H, T, L
+
+
+class FluctPlan:
+    """Thermally fluctuating grains of a grid (dust_fluct_plan): the level
+    distributions P[c, s, j] and the emission averaged over them."""
+
+    def __init__(self, grid, lev_T, lev_E):
+        self._keep = [np.ascontiguousarray(a, dtype=np.float64)
+                      for a in (grid.lam, grid.dlam, grid.c_abs, grid.weight, grid.size,
+                                lev_T, lev_E)]
+        lam, dlam, cabs, w, a, lt, le = self._keep
+        self.n_lambda = int(lam.shape[0])
+        self.n_grains = int(cabs.shape[0])
+        if lt.ndim != 2 or lt.shape != le.shape or lt.shape[0] != self.n_grains:
+            raise ValueError("lev_T and lev_E must both be [n_grains, n_levels]")
+        self.n_levels = int(lt.shape[1])
+        desc = GridDesc(self.n_lambda, self.n_grains, lam.ctypes.data, dlam.ctypes.data,
+                        cabs.ctypes.data, w.ctypes.data, a.ctypes.data)
+        lv = Levels(self.n_levels, lt.ctypes.data, le.ctypes.data)
+        h = _vp()
+        _check(lib().dust_fluct_plan_create(ctypes.byref(desc), ctypes.byref(lv),
+                                            ctypes.byref(h)))
+        self._h = h
+        import torch
+        self.device = torch.cuda.current_device()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dust_fluct_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve_P(self, J, P=None, counters=None, stream=None):
+        """P[c, s * n_levels + j] (float32 [C, >= S M]) from J[C, NL]."""
+        import torch
+        n = J.shape[0]
+        K = self.n_grains * self.n_levels
+        if P is None:
+            P = torch.empty((n, K), dtype=torch.float32, device=J.device)
+        pj, ldj = _rows(J, self.n_lambda, "J", n, self.device)
+        pp, ldp = _rows(P, K, "P", n, self.device)
+        pc = _counters(counters, self.device)
+        _check(lib().dust_fluct_solve_P(self._h, n, pj, ldj, pp, ldp, pc, _stream(stream)))
+        return P
+
+    def emit(self, P, m_dust=None, L=None, accumulate=False, stream=None):
+        """L[c, l] from the distributions; accumulate adds onto L."""
+        n = P.shape[0]
+        K = self.n_grains * self.n_levels
+        if L is None:
+            if accumulate:
+                raise ValueError("accumulate needs L")
+            import torch
+            L = torch.empty((n, self.n_lambda), dtype=torch.float32, device=P.device)
+        pp, ldp = _rows(P, K, "P", n, self.device)
+        pl, ldl = _rows(L, self.n_lambda, "L", n, self.device)
+        pm = _masses(m_dust, n, self.device)
+        _check(lib().dust_fluct_emit_sed(self._h, n, pp, ldp, pm, pl, ldl,
+                                         1 if accumulate else 0, _stream(stream)))
+        return L
 
 
 def _grid_arrays(plans, J, m_dust, T, L):

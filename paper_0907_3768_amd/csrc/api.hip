@@ -38,6 +38,9 @@ bool finite_nonneg(const double* a, int64_t n) {
     return true;
 }
 
+}  // namespace
+
+// Checks a grid descriptor (also used by the fluctuating-grain plan).
 dust_status validate_grid(const dust_grid_desc* g) {
     if (!g) return set_error(DUST_EINVAL, "grid descriptor is NULL");
     if (g->n_lambda < 1 || g->n_lambda > MAX_LAMBDA)
@@ -63,6 +66,8 @@ dust_status validate_grid(const dust_grid_desc* g) {
             return set_error(DUST_EINVAL, "size must be finite and > 0");
     return DUST_OK;
 }
+
+namespace {
 
 dust_status resolve_options(const dust_options* in, dust_options* o) {
     dust_options d;

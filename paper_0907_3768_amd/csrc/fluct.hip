@@ -1,0 +1,547 @@
+// Thermally fluctuating grains (the calculation Sections 2 and 6 name; see
+// dust.h): the steady-state probability of every enthalpy level of every
+// (cell, grain) pair under single-photon heating and continuous cooling, and
+// the emission averaged over it.
+//
+// Distribution (one wave per pair, FP64).  With photons ordered from the
+// shortest wavelength (largest energy eps) on, the upward rate from level i
+// to any level >= j is
+//   B[j][i] = sum_l R_l clamp((E_i + eps_l - E_{j-1}) / (E_j - E_{j-1}), 0, 1)
+// (a photon landing between E_{j-1} and E_j counts with the fraction of it
+// shared to level j).  With the prefix sums F0[n] = sum_{l<n} R_l and
+// F1[n] = sum_{l<n} R_l eps_l in LDS and n(x) = #{l : eps_l >= x} from a
+// per-grain table built with the plan, that is
+//   B[j][i] = F0[n2] + ((F1[n1] - F1[n2]) - a (F0[n1] - F0[n2])) / d,
+//   a = E_{j-1} - E_i, d = E_j - E_{j-1}, n1 = n(a), n2 = n(a + d):
+// two LDS reads and a few FP64 operations per (j, i) instead of a pass over
+// the wavelengths.  The flux balance across each level boundary then gives
+// the levels one by one, X_j = sum_{i<j} B[j][i] X_i / cool_j, with the
+// lanes over i and a wave sum; the running values are rescaled by exact
+// powers of two when they grow large, and P = X / sum X.
+//
+// Emission: L[c,l] = m_c sum_k P[c,k] Etab[k,l] over k = (grain, level), a
+// dense contraction (K = S M) on v_mfma_f32_16x16x4_f32 with a per-grain
+// emission table w_s C[s,l] B(lam_l, T_sj) built with the plan.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "device_common.h"
+
+namespace dust {
+
+dust_status validate_grid(const dust_grid_desc* g);  // api.hip
+
+namespace fluct {
+
+constexpr int MAX_LEVELS = 256;
+constexpr int MAX_LDS = 65536;          // bytes of one workgroup's prefix sums
+constexpr double TOP_PROBABILITY = 1e-6;  // counted when the top level holds more
+
+struct View {
+    int NL, S, M;
+    int K, Kp, NLp;       // K = S M; Kp = K rounded up to 16; NLp = NL rounded up to 64
+    const double* eps;    // [NL] photon energies h c / lam (J)
+    const double* kr;     // [S][NL] C dlam / eps: J times it is the photon rate
+    const double* E;      // [S][M] level enthalpies
+    const double* cool;   // [S][M] P(T_j) / (E_j - E_{j-1}), 0 at j = 0
+    const double* invd;   // [S][M] 1 / (E_j - E_{j-1}), 0 at j = 0
+    const int* cnt;       // [S][M][M] cnt[s][k][i] = #{l : eps_l >= E_k - E_i} (NL for i >= k)
+    const float* etab;    // [NLp][Kp] w_s C[s,l] B(lam_l, T_sj) 2^-ge, zero padded
+    float escale;         // 2^ge
+};
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// Plan tables.
+// ---------------------------------------------------------------------------
+struct Prep {
+    View v;
+    const double *lam, *dlam, *cabs, *w, *T;
+    double *eps, *kr, *cool, *invd;
+    int* cnt;
+    float* etab;
+    int ge;
+};
+
+// eps and kr: one thread per (grain, wavelength).
+__global__ __launch_bounds__(256) void prep_rates_kernel(Prep p) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)p.v.S * p.v.NL) return;
+    const int s = (int)(i / p.v.NL), l = (int)(i - (int64_t)s * p.v.NL);
+    const double eps = PLANCK_H * LIGHT_C / p.lam[l];
+    if (s == 0) p.eps[l] = eps;
+    p.kr[i] = p.cabs[i] * p.dlam[l] / eps;
+}
+
+// Cooling rates: one wave per (grain, level), the grain power of Eq. 7 at
+// T_j summed over the wavelengths by the lanes.
+__global__ __launch_bounds__(64) void prep_cool_kernel(Prep p) {
+    const int s = blockIdx.y, j = blockIdx.x;
+    const int M = p.v.M, NL = p.v.NL;
+    const double T = p.T[(int64_t)s * M + j];
+    double sum = 0.0;
+    if (j > 0) {
+        const double invT = rcp_f64(T);
+        for (int l = threadIdx.x; l < NL; l += 64) {
+            const double lam = p.lam[l];
+            const double em = expm1_pos(RAD_C2 / lam * invT);
+            const double lam2 = lam * lam;
+            const double b = (em < __builtin_inf()) ? RAD_C1 / (lam2 * lam2 * lam) / em : 0.0;
+            sum += p.cabs[(int64_t)s * NL + l] * p.dlam[l] * b;
+        }
+    }
+    sum = wave_sum_f64(sum);
+    if (threadIdx.x == 0) {
+        const int64_t o = (int64_t)s * M + j;
+        if (j == 0) {
+            p.cool[o] = 0.0;
+            p.invd[o] = 0.0;
+        } else {
+            const double d = p.v.E[o] - p.v.E[o - 1];
+            p.cool[o] = sum / d;
+            p.invd[o] = 1.0 / d;
+        }
+    }
+}
+
+// Photon counts: one thread per (grain, k, i); eps decreases with l, so the
+// count of eps_l >= x is the first l with eps_l < x.
+__global__ __launch_bounds__(256) void prep_count_kernel(Prep p) {
+    const int M = p.v.M, NL = p.v.NL;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)p.v.S * M * M) return;
+    const int s = (int)(t / ((int64_t)M * M));
+    const int r = (int)(t - (int64_t)s * M * M);
+    const int k = r / M, i = r - k * M;
+    int n = NL;
+    if (i < k) {
+        const double x = p.v.E[(int64_t)s * M + k] - p.v.E[(int64_t)s * M + i];
+        int lo = 0, hi = NL;  // first l in [0, NL] with eps_l < x
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (p.eps[mid] < x) hi = mid; else lo = mid + 1;
+        }
+        n = lo;
+    }
+    p.cnt[t] = n;
+}
+
+// Emission table: one thread per (wavelength, (grain, level)).
+__global__ __launch_bounds__(256) void prep_etab_kernel(Prep p) {
+    const View& v = p.v;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)v.NLp * v.Kp) return;
+    const int l = (int)(t / v.Kp), k = (int)(t - (int64_t)l * v.Kp);
+    float val = 0.0f;
+    if (l < v.NL && k < v.K) {
+        const int s = k / v.M;
+        const double T = p.T[k];  // [S][M] flattened: k = s M + j
+        if (T > 0.0) {
+            const double lam = p.lam[l];
+            const double em = expm1_pos(RAD_C2 / lam * rcp_f64(T));
+            const double lam2 = lam * lam;
+            const double b = (em < __builtin_inf()) ? RAD_C1 / (lam2 * lam2 * lam) / em : 0.0;
+            val = (float)ldexp(p.w[s] * p.cabs[(int64_t)s * v.NL + l] * b, -p.ge);
+        }
+    }
+    p.etab[t] = val;
+}
+
+// ---------------------------------------------------------------------------
+// The distribution of one pair per wave; Q = levels per lane (M <= 64 Q).
+// ---------------------------------------------------------------------------
+template <int Q>
+__global__ __launch_bounds__(64) void solve_kernel(View v, int64_t C, const float* __restrict__ J,
+                                                   int64_t ldj, float* __restrict__ P, int64_t ldp,
+                                                   dust_counters* cnt) {
+    extern __shared__ double2 sF[];  // [NL + 1]: (F0, F1) prefix sums
+    const int lane = threadIdx.x;
+    const int64_t pair = blockIdx.x;
+    const int s = (int)(pair % v.S);
+    const int64_t c = pair / v.S;
+    const int NL = v.NL, M = v.M;
+    // 1. photon rates and their prefix sums, shortest wavelength first
+    const float* jr = J + c * ldj;
+    const double* kr = v.kr + (int64_t)s * NL;
+    double carry0 = 0.0, carry1 = 0.0;
+    bool bad = false;
+    if (lane == 0) sF[0] = make_double2(0.0, 0.0);
+    for (int l0 = 0; l0 < NL; l0 += 64) {
+        const int l = l0 + lane;
+        double r = 0.0, re = 0.0;
+        if (l < NL) {
+            const float jv = jr[l];
+            if (!(jv >= 0.0f) || __builtin_isinf(jv)) bad = true;
+            r = (double)jv * kr[l];
+            re = r * v.eps[l];
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double a = __shfl_up(r, d, 64), b = __shfl_up(re, d, 64);
+            if (lane >= d) {
+                r += a;
+                re += b;
+            }
+        }
+        if (l < NL) sF[l + 1] = make_double2(carry0 + r, carry1 + re);
+        carry0 += __shfl(r, 63, 64);
+        carry1 += __shfl(re, 63, 64);
+    }
+    const bool any_bad = __ballot(bad) != 0;
+    __syncthreads();
+    // 2. levels upwards; lane holds levels lane + 64 q
+    const double* Es = v.E + (int64_t)s * M;
+    const int* cn = v.cnt + (int64_t)s * M * M;
+    const double* cool = v.cool + (int64_t)s * M;
+    const double* invd = v.invd + (int64_t)s * M;
+    double X[Q], Ei[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = lane + 64 * q;
+        Ei[q] = i < M ? Es[i] : 0.0;
+        X[q] = (i == 0) ? 1.0 : 0.0;
+    }
+    for (int j = 1; j < M; ++j) {
+        const double Ejm1 = Es[j - 1];
+        const double dinv = invd[j];
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (64 * q >= j) break;  // uniform
+            const int i = lane + 64 * q;
+            if (i < j) {
+                const int n1 = cn[(j - 1) * M + i];  // eps >= E_{j-1} - E_i (NL when i = j - 1)
+                const int n2 = cn[j * M + i];        // eps >= E_j - E_i
+                const double2 f1 = sF[n1], f2 = sF[n2];
+                const double a = Ejm1 - Ei[q];
+                const double B = f2.x + ((f1.y - f2.y) - a * (f1.x - f2.x)) * dinv;
+                sum = fma(B, X[q], sum);
+            }
+        }
+        sum = wave_sum_f64(sum);
+        const double xj = sum / cool[j];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if ((j >> 6) == q && lane == (j & 63)) X[q] = xj;
+        if (xj > 0x1p500) {  // uniform: keep the running values in range (exact)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) X[q] = ldexp(X[q], -500);
+        }
+    }
+    // 3. normalise
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) tot += X[q];
+    tot = wave_sum_f64(tot);
+    const double inv = 1.0 / tot;
+    float* pr = P + c * ldp + (int64_t)s * M;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = lane + 64 * q;
+        if (i < M) {
+            const double pv = X[q] * inv;
+            pr[i] = any_bad ? __builtin_nanf("") : (float)pv;
+            if (cnt && !any_bad && i == M - 1 && pv > TOP_PROBABILITY) count(&cnt->n_out_of_table);
+        }
+    }
+    if (cnt && any_bad && lane == 0) count(&cnt->n_nonfinite);
+}
+
+// ---------------------------------------------------------------------------
+// Emission: a workgroup takes 16 cells x 64 wavelengths, each wave 16 of the
+// wavelengths; blocks run wavelength block fastest, so the cells' rows of P
+// are shared in L2 by consecutive workgroups.  MFMA i of a 16-wide k step
+// takes k = k0 + 4 q + i in slot q of both operands (lane = 16 q + row).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void emit_kernel(View v, int64_t C, const float* __restrict__ P,
+                                                   int64_t ldp, const float* __restrict__ m,
+                                                   float* __restrict__ L, int64_t ldl,
+                                                   int accumulate) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nlb = v.NLp / 64;
+    const int64_t b = blockIdx.x;
+    const int lb = (int)(b % nlb);
+    const int64_t c0 = (b / nlb) * 16;
+    const int row = lane & 15, q = lane >> 4;
+    const int l = lb * 64 + wave * 16 + row;  // < NLp
+    const int64_t cr = c0 + row;
+    const bool c_ok = cr < C;
+    const float* pr = P + (c_ok ? cr : 0) * ldp;
+    const float* er = v.etab + (int64_t)l * v.Kp;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < v.K; k0 += 16) {
+        const int kq = k0 + 4 * q;
+        float a[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = (c_ok && kq + t < v.K) ? pr[kq + t] : 0.0f;
+        const float4 e = *reinterpret_cast<const float4*>(er + kq);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], e.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], e.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], e.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], e.w, acc, 0, 0, 0);
+    }
+    if (l >= v.NL) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t cc = c0 + 4 * q + r;
+        if (cc < C) {
+            const float val = acc[r] * ((m ? m[cc] : 1.0f) * v.escale);
+            float* dst = L + cc * ldl + l;
+            *dst = accumulate ? *dst + val : val;
+        }
+    }
+}
+
+int round_up(int x, int mlt) { return (x + mlt - 1) / mlt * mlt; }
+
+}  // namespace fluct
+}  // namespace dust
+
+struct dust_fluct_plan {
+    int device;
+    double *d_lam, *d_dlam, *d_cabs, *d_w, *d_T;
+    double *d_E, *d_eps, *d_kr, *d_cool, *d_invd;
+    int* d_cnt;
+    float* d_etab;
+    dust::fluct::View view;
+};
+
+namespace dust {
+namespace fluct {
+
+void free_plan(dust_fluct_plan* p) {
+    if (!p) return;
+    void* ptrs[] = {p->d_lam, p->d_dlam, p->d_cabs, p->d_w, p->d_T, p->d_E,
+                    p->d_eps, p->d_kr, p->d_cool, p->d_invd, p->d_cnt, p->d_etab};
+    for (void* x : ptrs)
+        if (x) (void)hipFree(x);
+    delete p;
+}
+
+dust_status validate_levels(const dust_levels* lv, int S) {
+    if (!lv) return set_error(DUST_EINVAL, "levels descriptor is NULL");
+    const int M = lv->n_levels;
+    if (M < 2 || M > MAX_LEVELS) return set_error(DUST_EINVAL, "n_levels must be in [2, 256]");
+    if (!lv->T || !lv->E) return set_error(DUST_EINVAL, "a level table pointer is NULL");
+    for (int s = 0; s < S; ++s) {
+        const double* T = lv->T + (int64_t)s * M;
+        const double* E = lv->E + (int64_t)s * M;
+        if (T[0] != 0.0 || E[0] != 0.0)
+            return set_error(DUST_EINVAL, "level 0 must be the ground state (T = 0, E = 0)");
+        for (int j = 1; j < M; ++j) {
+            if (!isfinite(T[j]) || !isfinite(E[j]) || !(T[j] > T[j - 1]) || !(E[j] > E[j - 1]))
+                return set_error(DUST_EINVAL,
+                                 "level temperatures and enthalpies must be finite and strictly "
+                                 "increasing");
+        }
+    }
+    return DUST_OK;
+}
+
+}  // namespace fluct
+}  // namespace dust
+
+using namespace dust;
+using namespace dust::fluct;
+
+extern "C" {
+
+dust_status dust_fluct_plan_create(const dust_grid_desc* g, const dust_levels* lv,
+                                   dust_fluct_plan** out) {
+    clear_error();
+    if (!out) return set_error(DUST_EINVAL, "out is NULL");
+    *out = nullptr;
+    dust_status st = validate_grid(g);
+    if (st != DUST_OK) return st;
+    if ((st = validate_levels(lv, g->n_grains)) != DUST_OK) return st;
+    const int NL = g->n_lambda, S = g->n_grains, M = lv->n_levels;
+    if ((size_t)(NL + 1) * sizeof(double2) > (size_t)MAX_LDS)
+        return set_error(DUST_EUNSUPPORTED,
+                         "fluctuating grains take at most 4095 wavelengths (one workgroup's "
+                         "prefix sums in LDS)");
+    if ((int64_t)S * M > (1 << 20))
+        return set_error(DUST_EUNSUPPORTED, "n_grains x n_levels above 2^20");
+    // one power of two for the emission table: with B(lam, T) <= c1 lam^-4 T / c2
+    // (Rayleigh-Jeans) its entries stay below 2^0
+    double emax = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const double tmax = lv->T[(int64_t)s * M + M - 1];
+        for (int l = 0; l < NL; ++l) {
+            const double lam = g->lambda[l];
+            emax = fmax(emax, g->weight[s] * g->c_abs[(int64_t)s * NL + l] * RAD_C1 * tmax /
+                                  (RAD_C2 * lam * lam * lam * lam));
+        }
+    }
+    int ge = 0;
+    if (emax > 0.0) (void)frexp(emax, &ge);
+    if (ge < -120 || ge > 120)
+        return set_error(DUST_EUNSUPPORTED, "emission table outside the FP32 range");
+
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_error(e, "hipGetDevice");
+    dust_fluct_plan* p = new dust_fluct_plan;
+    memset(p, 0, sizeof *p);
+    p->device = dev;
+    View& v = p->view;
+    v.NL = NL;
+    v.S = S;
+    v.M = M;
+    v.K = S * M;
+    v.Kp = round_up(v.K, 16);
+    v.NLp = round_up(NL, 64);
+    v.escale = ldexpf(1.0f, ge);
+    const size_t nSM = (size_t)S * M;
+#define FALLOC(ptr, n)                                                     \
+    if ((e = hipMalloc((void**)&(ptr), sizeof(*(ptr)) * (n))) != hipSuccess) { \
+        free_plan(p);                                                      \
+        return hip_error(e, "hipMalloc (" #ptr ")");                       \
+    }
+    FALLOC(p->d_lam, NL);
+    FALLOC(p->d_dlam, NL);
+    FALLOC(p->d_cabs, (size_t)S * NL);
+    FALLOC(p->d_w, S);
+    FALLOC(p->d_T, nSM);
+    FALLOC(p->d_E, nSM);
+    FALLOC(p->d_eps, NL);
+    FALLOC(p->d_kr, (size_t)S * NL);
+    FALLOC(p->d_cool, nSM);
+    FALLOC(p->d_invd, nSM);
+    FALLOC(p->d_cnt, nSM * M);
+    FALLOC(p->d_etab, (size_t)v.NLp * v.Kp);
+#undef FALLOC
+    struct Up { void* d; const void* h; size_t n; } ups[] = {
+        {p->d_lam, g->lambda, sizeof(double) * NL},
+        {p->d_dlam, g->dlambda, sizeof(double) * NL},
+        {p->d_cabs, g->c_abs, sizeof(double) * S * (size_t)NL},
+        {p->d_w, g->weight, sizeof(double) * S},
+        {p->d_T, lv->T, sizeof(double) * nSM},
+        {p->d_E, lv->E, sizeof(double) * nSM},
+    };
+    for (const Up& u : ups) {
+        if ((e = hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice)) != hipSuccess) {
+            free_plan(p);
+            return hip_error(e, "hipMemcpy (fluctuating-grain plan)");
+        }
+    }
+    v.eps = p->d_eps;
+    v.kr = p->d_kr;
+    v.E = p->d_E;
+    v.cool = p->d_cool;
+    v.invd = p->d_invd;
+    v.cnt = p->d_cnt;
+    v.etab = p->d_etab;
+    Prep pr{v, p->d_lam, p->d_dlam, p->d_cabs, p->d_w, p->d_T,
+            p->d_eps, p->d_kr, p->d_cool, p->d_invd, p->d_cnt, p->d_etab, ge};
+    const int64_t n_rates = (int64_t)S * NL, n_cnt = (int64_t)nSM * M,
+                  n_etab = (int64_t)v.NLp * v.Kp;
+    hipLaunchKernelGGL(prep_rates_kernel, dim3((unsigned)((n_rates + 255) / 256)), dim3(256), 0,
+                       nullptr, pr);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(prep_cool_kernel, dim3(M, S), dim3(64), 0, nullptr, pr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {  // after the rates: the counts read eps
+        hipLaunchKernelGGL(prep_count_kernel, dim3((unsigned)((n_cnt + 255) / 256)), dim3(256), 0,
+                           nullptr, pr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(prep_etab_kernel, dim3((unsigned)((n_etab + 255) / 256)), dim3(256), 0,
+                           nullptr, pr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_error(e, "fluctuating-grain plan kernels");
+    }
+    // every level above the ground must radiate (its cooling rate divides)
+    std::vector<double> cool(nSM);
+    if ((e = hipMemcpy(cool.data(), p->d_cool, sizeof(double) * nSM, hipMemcpyDeviceToHost)) !=
+        hipSuccess) {
+        free_plan(p);
+        return hip_error(e, "hipMemcpy (cooling rates)");
+    }
+    for (int s = 0; s < S; ++s)
+        for (int j = 1; j < M; ++j)
+            if (!(cool[(size_t)s * M + j] > 0.0) || !isfinite(cool[(size_t)s * M + j])) {
+                free_plan(p);
+                return set_error(DUST_EINVAL,
+                                 "grain " + std::to_string(s) + " level " + std::to_string(j) +
+                                     ": the grain radiates no power at that temperature in FP64 "
+                                     "(too cold for the wavelength grid)");
+            }
+    *out = p;
+    return DUST_OK;
+}
+
+dust_status dust_fluct_plan_destroy(dust_fluct_plan* p) {
+    clear_error();
+    if (!p) return DUST_OK;
+    const hipError_t e = hipDeviceSynchronize();
+    free_plan(p);
+    return e == hipSuccess ? DUST_OK : hip_error(e, "hipDeviceSynchronize");
+}
+
+dust_status dust_fluct_solve_P(dust_fluct_plan* p, int64_t C, const float* J, int64_t ldj,
+                               float* P, int64_t ldp, dust_counters* cnt, void* stream) {
+    clear_error();
+    if (!p) return set_error(DUST_EINVAL, "plan is NULL");
+    if (C < 0) return set_error(DUST_EINVAL, "n_cells must be >= 0");
+    const View& v = p->view;
+    if (C * (int64_t)v.S > INT32_MAX)
+        return set_error(DUST_EUNSUPPORTED, "n_cells x n_grains above 2^31 - 1");
+    if (cnt && ((uintptr_t)cnt & 7u)) return set_error(DUST_EINVAL, "counters must be 8-byte aligned");
+    if (C == 0) return DUST_OK;
+    if (!J || !P) return set_error(DUST_EINVAL, "J or P is NULL");
+    if ((((uintptr_t)J) | ((uintptr_t)P)) & 3u)
+        return set_error(DUST_EINVAL, "J and P must be 4-byte aligned");
+    if (ldj < v.NL) return set_error(DUST_EINVAL, "leading dimension of J is smaller than its row");
+    if (ldp < (int64_t)v.K)
+        return set_error(DUST_EINVAL, "leading dimension of P is smaller than n_grains x n_levels");
+    const hipStream_t st = (hipStream_t)stream;
+    const size_t lds = sizeof(double2) * (size_t)(v.NL + 1);
+    const dim3 grid((unsigned)(C * v.S));
+    if (v.M <= 64)
+        hipLaunchKernelGGL(solve_kernel<1>, grid, dim3(64), lds, st, v, C, J, ldj, P, ldp, cnt);
+    else if (v.M <= 128)
+        hipLaunchKernelGGL(solve_kernel<2>, grid, dim3(64), lds, st, v, C, J, ldj, P, ldp, cnt);
+    else
+        hipLaunchKernelGGL(solve_kernel<4>, grid, dim3(64), lds, st, v, C, J, ldj, P, ldp, cnt);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DUST_OK : hip_error(e, "fluctuating-grain distribution launch");
+}
+
+dust_status dust_fluct_emit_sed(dust_fluct_plan* p, int64_t C, const float* P, int64_t ldp,
+                                const float* m, float* L, int64_t ldl, int32_t accumulate,
+                                void* stream) {
+    clear_error();
+    if (!p) return set_error(DUST_EINVAL, "plan is NULL");
+    if (C < 0) return set_error(DUST_EINVAL, "n_cells must be >= 0");
+    const View& v = p->view;
+    if (C == 0) return DUST_OK;
+    if (!P || !L) return set_error(DUST_EINVAL, "P or L is NULL");
+    if ((((uintptr_t)P) | ((uintptr_t)L) | ((uintptr_t)m)) & 3u)
+        return set_error(DUST_EINVAL, "P, L and m_dust must be 4-byte aligned");
+    if (ldp < (int64_t)v.K)
+        return set_error(DUST_EINVAL, "leading dimension of P is smaller than n_grains x n_levels");
+    if (ldl < v.NL) return set_error(DUST_EINVAL, "leading dimension of L is smaller than its row");
+    const int64_t blocks = (C + 15) / 16 * (v.NLp / 64);
+    if (blocks > INT32_MAX) return set_error(DUST_EUNSUPPORTED, "too many cells");
+    hipLaunchKernelGGL(emit_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, v, C,
+                       P, ldp, m, L, ldl, accumulate ? 1 : 0);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DUST_OK : hip_error(e, "fluctuating-grain emission launch");
+}
+
+}  // extern "C"

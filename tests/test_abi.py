@@ -256,3 +256,47 @@ def test_batch_run_noalloc_limits(L):
     args = [v(z), 1, v(nc1), v(z), v(ld), v(z), v(z), v(ld), v(z), v(ld), None, None]
     assert L.dust_batch_run_noalloc(*args) == dust.DUST_EINVAL
     assert b"tiles" in L.dust_last_error()
+
+
+def _levels(S, M, T=None, E=None):
+    T = np.concatenate([[0.0], np.geomspace(3.0, 2000.0, M - 1)]) if T is None else T
+    E = np.concatenate([[0.0], np.geomspace(1e-22, 1e-17, M - 1)]) if E is None else E
+    keep = [np.ascontiguousarray(np.tile(x, (S, 1)), dtype=np.float64) for x in (T, E)]
+    return dust.Levels(M, keep[0].ctypes.data, keep[1].ctypes.data), keep
+
+
+@pytest.mark.parametrize("case", ["m1", "m_big", "t0", "e0", "e_flat", "t_nan", "null"])
+def test_fluct_plan_rejects_bad_levels(L, case):
+    """The fluctuating-grain plan checks its levels before any HIP call."""
+    d, keep = _desc(nl=8, s=2)
+    M = 6
+    T = np.concatenate([[0.0], np.geomspace(3.0, 2000.0, M - 1)])
+    E = np.concatenate([[0.0], np.geomspace(1e-22, 1e-17, M - 1)])
+    if case == "m1":
+        M, T, E = 1, T[:1], E[:1]
+    if case == "m_big":
+        M = 257
+        T = np.concatenate([[0.0], np.geomspace(3.0, 2000.0, M - 1)])
+        E = np.concatenate([[0.0], np.geomspace(1e-22, 1e-17, M - 1)])
+    if case == "t0":
+        T = T.copy(); T[0] = 1.0
+    if case == "e0":
+        E = E.copy(); E[0] = 1e-30
+    if case == "e_flat":
+        E = E.copy(); E[3] = E[2]
+    if case == "t_nan":
+        T = T.copy(); T[4] = np.nan
+    lv, keep2 = _levels(2, M, T, E)
+    if case == "null":
+        lv.E = None
+    h = ctypes.c_void_p()
+    assert L.dust_fluct_plan_create(ctypes.byref(d), ctypes.byref(lv), ctypes.byref(h)) == \
+        dust.DUST_EINVAL
+    assert h.value is None and len(L.dust_last_error()) > 0
+
+
+def test_fluct_calls_reject_null_plan(L):
+    nul = ctypes.c_void_p(0)
+    assert L.dust_fluct_solve_P(nul, 4, nul, 8, nul, 8, nul, nul) == dust.DUST_EINVAL
+    assert L.dust_fluct_emit_sed(nul, 4, nul, 8, nul, nul, 8, 0, nul) == dust.DUST_EINVAL
+    assert L.dust_fluct_plan_destroy(None) == dust.DUST_OK

@@ -34,3 +34,15 @@ def test_committed_traffic_entries_are_complete():
 def test_alu_peak_follows_from_unit_counts():
     # 256 CUs x 4 SIMDs x 64 lanes per 8 cycles at 2.4 GHz, two transcendentals per term
     assert abs(bench.TERM_PEAK_PER_S - 256 * 4 * 2.4e9 * 64 / 8 / 2) < 1e3
+
+
+def test_host_rows_refuses_indices_outside_the_tensor():
+    import numpy as np
+    import pytest
+    import torch
+    t = torch.arange(12.0).reshape(4, 3)
+    assert bench.host_rows(t, [0, 3]).tolist() == [[0.0, 1.0, 2.0], [9.0, 10.0, 11.0]]
+    with pytest.raises(IndexError):
+        bench.host_rows(t, np.array([1, 4]))
+    with pytest.raises(IndexError):
+        bench.host_rows(t, np.array([-1]))
