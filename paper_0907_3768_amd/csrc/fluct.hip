@@ -15,13 +15,15 @@
 //   a = E_{j-1} - E_i, d = E_j - E_{j-1}, n1 = n(a), n2 = n(a + d):
 // two LDS reads and a few FP64 operations per (j, i) instead of a pass over
 // the wavelengths.  The flux balance across each level boundary then gives
-// the levels one by one, X_j = sum_{i<j} B[j][i] X_i / cool_j, with the
-// lanes over i and a wave sum; the running values are rescaled by exact
+// the levels one by one, X_j = sum_{i<j} B[j][i] X_i / cool_j: the lanes
+// hold the upper levels j and collect their sums as the levels below them
+// become final (no wave reduction); the running values are rescaled by exact
 // powers of two when they grow large, and P = X / sum X.
 //
 // Emission: L[c,l] = m_c sum_k P[c,k] Etab[k,l] over k = (grain, level), a
 // dense contraction (K = S M) on v_mfma_f32_16x16x4_f32 with a per-grain
 // emission table w_s C[s,l] B(lam_l, T_sj) built with the plan.
+
 #include <math.h>
 #include <string.h>
 
@@ -42,13 +44,13 @@ constexpr double TOP_PROBABILITY = 1e-6;  // counted when the top level holds mo
 
 struct View {
     int NL, S, M;
-    int K, Kp, NLp;       // K = S M; Kp = K rounded up to 16; NLp = NL rounded up to 64
+    int K, Kp, NLp;       // K = S M; Kp = K rounded up to 16; NLp = NL rounded up to 128
     const double* eps;    // [NL] photon energies h c / lam (J)
     const double* kr;     // [S][NL] C dlam / eps: J times it is the photon rate
     const double* E;      // [S][M] level enthalpies
-    const double* cool;   // [S][M] P(T_j) / (E_j - E_{j-1}), 0 at j = 0
+    const double* rcool;  // [S][M] (E_j - E_{j-1}) / P(T_j): 1 / the cooling rate, 0 at j = 0
     const double* invd;   // [S][M] 1 / (E_j - E_{j-1}), 0 at j = 0
-    const int* cnt;       // [S][M][M] cnt[s][k][i] = #{l : eps_l >= E_k - E_i} (NL for i >= k)
+    const int* cnt;       // [S][M][M] cnt[s][i][k] = #{l : eps_l >= E_k - E_i} (NL for k <= i)
     const float* etab;    // [NLp][Kp] w_s C[s,l] B(lam_l, T_sj) 2^-ge, zero padded
     float escale;         // 2^ge
 };
@@ -65,7 +67,7 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
 struct Prep {
     View v;
     const double *lam, *dlam, *cabs, *w, *T;
-    double *eps, *kr, *cool, *invd;
+    double *eps, *kr, *rcool, *invd;
     int* cnt;
     float* etab;
     int ge;
@@ -81,8 +83,8 @@ __global__ __launch_bounds__(256) void prep_rates_kernel(Prep p) {
     p.kr[i] = p.cabs[i] * p.dlam[l] / eps;
 }
 
-// Cooling rates: one wave per (grain, level), the grain power of Eq. 7 at
-// T_j summed over the wavelengths by the lanes.
+// Cooling rates (their reciprocals): one wave per (grain, level), the grain
+// power of Eq. 7 at T_j summed over the wavelengths by the lanes.
 __global__ __launch_bounds__(64) void prep_cool_kernel(Prep p) {
     const int s = blockIdx.y, j = blockIdx.x;
     const int M = p.v.M, NL = p.v.NL;
@@ -102,17 +104,17 @@ __global__ __launch_bounds__(64) void prep_cool_kernel(Prep p) {
     if (threadIdx.x == 0) {
         const int64_t o = (int64_t)s * M + j;
         if (j == 0) {
-            p.cool[o] = 0.0;
+            p.rcool[o] = 0.0;
             p.invd[o] = 0.0;
         } else {
             const double d = p.v.E[o] - p.v.E[o - 1];
-            p.cool[o] = sum / d;
+            p.rcool[o] = d / sum;  // inf when the level radiates nothing (refused by the host)
             p.invd[o] = 1.0 / d;
         }
     }
 }
 
-// Photon counts: one thread per (grain, k, i); eps decreases with l, so the
+// Photon counts: one thread per (grain, i, k); eps decreases with l, so the
 // count of eps_l >= x is the first l with eps_l < x.
 __global__ __launch_bounds__(256) void prep_count_kernel(Prep p) {
     const int M = p.v.M, NL = p.v.NL;
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void prep_count_kernel(Prep p) {
     if (t >= (int64_t)p.v.S * M * M) return;
     const int s = (int)(t / ((int64_t)M * M));
     const int r = (int)(t - (int64_t)s * M * M);
-    const int k = r / M, i = r - k * M;
+    const int i = r / M, k = r - i * M;
     int n = NL;
     if (i < k) {
         const double x = p.v.E[(int64_t)s * M + k] - p.v.E[(int64_t)s * M + i];
@@ -157,7 +159,28 @@ __global__ __launch_bounds__(256) void prep_etab_kernel(Prep p) {
 
 // ---------------------------------------------------------------------------
 // The distribution of one pair per wave; Q = levels per lane (M <= 64 Q).
+//
+// Lanes over the upper level j: acc_j collects sum_{i<j} B[j][i] X_i.  Level
+// i is final once every level below it has been added, so the levels are
+// taken in order: X_i = acc_i / cool_i is read from lane i, and every lane
+// j > i adds B[j][i] X_i.  No wave reduction is needed; the rates of a step
+// depend only on the plan and the pair's prefix sums, not on X.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+template <int Q>
+__device__ __forceinline__ double pick(const double (&a)[Q], int q) {
+    double r = a[0];
+#pragma unroll
+    for (int k = 1; k < Q; ++k)
+        if (q == k) r = a[k];
+    return r;
+}
+
 template <int Q>
 __global__ __launch_bounds__(64) void solve_kernel(View v, int64_t C, const float* __restrict__ J,
                                                    int64_t ldj, float* __restrict__ P, int64_t ldp,
@@ -192,48 +215,56 @@ __global__ __launch_bounds__(64) void solve_kernel(View v, int64_t C, const floa
             }
         }
         if (l < NL) sF[l + 1] = make_double2(carry0 + r, carry1 + re);
-        carry0 += __shfl(r, 63, 64);
-        carry1 += __shfl(re, 63, 64);
+        carry0 += readlane_f64(r, 63);
+        carry1 += readlane_f64(re, 63);
     }
     const bool any_bad = __ballot(bad) != 0;
     __syncthreads();
-    // 2. levels upwards; lane holds levels lane + 64 q
+    // 2. levels in order; lane holds upper levels j = lane + 64 q
     const double* Es = v.E + (int64_t)s * M;
+    const double* rcool = v.rcool + (int64_t)s * M;
     const int* cn = v.cnt + (int64_t)s * M * M;
-    const double* cool = v.cool + (int64_t)s * M;
-    const double* invd = v.invd + (int64_t)s * M;
-    double X[Q], Ei[Q];
+    double acc[Q], X[Q], Ejm1[Q], dinv[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int i = lane + 64 * q;
-        Ei[q] = i < M ? Es[i] : 0.0;
-        X[q] = (i == 0) ? 1.0 : 0.0;
+        const int j = lane + 64 * q;
+        const bool ok = j >= 1 && j < M;
+        acc[q] = 0.0;
+        X[q] = 0.0;
+        Ejm1[q] = ok ? Es[j - 1] : 0.0;
+        dinv[q] = ok ? v.invd[(int64_t)s * M + j] : 0.0;
     }
-    for (int j = 1; j < M; ++j) {
-        const double Ejm1 = Es[j - 1];
-        const double dinv = invd[j];
-        double sum = 0.0;
+    double xi = 1.0;  // X_0
+    for (int i = 0; i < M; ++i) {
+        if (i > 0) {
+            xi = readlane_f64(pick<Q>(acc, i >> 6), i & 63) * rcool[i];
+            if (xi > 0x1p500) {  // uniform: keep the running values in range (exact)
+                xi = ldexp(xi, -500);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (64 * q >= j) break;  // uniform
-            const int i = lane + 64 * q;
-            if (i < j) {
-                const int n1 = cn[(j - 1) * M + i];  // eps >= E_{j-1} - E_i (NL when i = j - 1)
-                const int n2 = cn[j * M + i];        // eps >= E_j - E_i
-                const double2 f1 = sF[n1], f2 = sF[n2];
-                const double a = Ejm1 - Ei[q];
-                const double B = f2.x + ((f1.y - f2.y) - a * (f1.x - f2.x)) * dinv;
-                sum = fma(B, X[q], sum);
+                for (int q = 0; q < Q; ++q) {
+                    acc[q] = ldexp(acc[q], -500);
+                    X[q] = ldexp(X[q], -500);
+                }
             }
         }
-        sum = wave_sum_f64(sum);
-        const double xj = sum / cool[j];
 #pragma unroll
         for (int q = 0; q < Q; ++q)
-            if ((j >> 6) == q && lane == (j & 63)) X[q] = xj;
-        if (xj > 0x1p500) {  // uniform: keep the running values in range (exact)
+            if ((i >> 6) == q && lane == (i & 63)) X[q] = xi;
+        if (i == M - 1) break;
+        const double Ei = Es[i];
+        const int* row = cn + (int64_t)i * M;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) X[q] = ldexp(X[q], -500);
+        for (int q = 0; q < Q; ++q) {
+            if (64 * q + 63 <= i) continue;  // uniform: every level of this chunk is at or below i
+            const int j = lane + 64 * q;
+            if (j > i && j < M) {
+                const int n1 = row[j - 1];  // eps >= E_{j-1} - E_i (NL when j - 1 = i)
+                const int n2 = row[j];      // eps >= E_j - E_i
+                const double2 f1 = sF[n1], f2 = sF[n2];
+                const double a = Ejm1[q] - Ei;
+                const double B = f2.x + ((f1.y - f2.y) - a * (f1.x - f2.x)) * dinv[q];
+                acc[q] = fma(B, xi, acc[q]);
+            }
         }
     }
     // 3. normalise
@@ -256,46 +287,69 @@ __global__ __launch_bounds__(64) void solve_kernel(View v, int64_t C, const floa
 }
 
 // ---------------------------------------------------------------------------
-// Emission: a workgroup takes 16 cells x 64 wavelengths, each wave 16 of the
-// wavelengths; blocks run wavelength block fastest, so the cells' rows of P
-// are shared in L2 by consecutive workgroups.  MFMA i of a 16-wide k step
-// takes k = k0 + 4 q + i in slot q of both operands (lane = 16 q + row).
+// Emission: a workgroup takes 16 cells x 128 wavelengths, each wave 32 of the
+// wavelengths as two 16-wide MFMA blocks that share the cells' fragment of P;
+// blocks run wavelength block fastest, so the cells' rows of P are shared in
+// L2 by consecutive workgroups.  MFMA i of a 16-wide k step takes
+// k = k0 + 4 q + i in slot q of both operands (lane = 16 q + row).  VEC: P's
+// rows are 16-byte aligned and K is a multiple of 4, so a lane's four k of a
+// step are one float4.
 // ---------------------------------------------------------------------------
+template <bool VEC>
 __global__ __launch_bounds__(256) void emit_kernel(View v, int64_t C, const float* __restrict__ P,
                                                    int64_t ldp, const float* __restrict__ m,
                                                    float* __restrict__ L, int64_t ldl,
                                                    int accumulate) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nlb = v.NLp / 64;
+    const int nlb = v.NLp / 128;
     const int64_t b = blockIdx.x;
     const int lb = (int)(b % nlb);
     const int64_t c0 = (b / nlb) * 16;
     const int row = lane & 15, q = lane >> 4;
-    const int l = lb * 64 + wave * 16 + row;  // < NLp
+    const int l0 = lb * 128 + wave * 32;  // this wave: wavelengths l0 + row and l0 + 16 + row
     const int64_t cr = c0 + row;
     const bool c_ok = cr < C;
     const float* pr = P + (c_ok ? cr : 0) * ldp;
-    const float* er = v.etab + (int64_t)l * v.Kp;
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float* e0 = v.etab + (int64_t)(l0 + row) * v.Kp;
+    const float* e1 = e0 + (int64_t)16 * v.Kp;
+    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll 2
     for (int k0 = 0; k0 < v.K; k0 += 16) {
         const int kq = k0 + 4 * q;
-        float a[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) a[t] = (c_ok && kq + t < v.K) ? pr[kq + t] : 0.0f;
-        const float4 e = *reinterpret_cast<const float4*>(er + kq);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], e.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], e.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], e.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], e.w, acc, 0, 0, 0);
+        float4 a;
+        if constexpr (VEC) {
+            a = (c_ok && kq < v.K) ? *reinterpret_cast<const float4*>(pr + kq)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            a.x = (c_ok && kq < v.K) ? pr[kq] : 0.0f;
+            a.y = (c_ok && kq + 1 < v.K) ? pr[kq + 1] : 0.0f;
+            a.z = (c_ok && kq + 2 < v.K) ? pr[kq + 2] : 0.0f;
+            a.w = (c_ok && kq + 3 < v.K) ? pr[kq + 3] : 0.0f;
+        }
+        const float4 x0 = *reinterpret_cast<const float4*>(e0 + kq);
+        const float4 x1 = *reinterpret_cast<const float4*>(e1 + kq);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x0.x, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x1.x, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x0.y, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x1.y, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, x0.z, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, x1.z, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, x0.w, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, x1.w, acc1, 0, 0, 0);
     }
-    if (l >= v.NL) return;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int64_t cc = c0 + 4 * q + r;
-        if (cc < C) {
-            const float val = acc[r] * ((m ? m[cc] : 1.0f) * v.escale);
-            float* dst = L + cc * ldl + l;
-            *dst = accumulate ? *dst + val : val;
+        if (cc >= C) continue;
+        const float scale = (m ? m[cc] : 1.0f) * v.escale;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int l = l0 + 16 * h + row;
+            if (l < v.NL) {
+                const float val = (h ? acc1[r] : acc0[r]) * scale;
+                float* dst = L + cc * ldl + l;
+                *dst = accumulate ? *dst + val : val;
+            }
         }
     }
 }
@@ -308,7 +362,7 @@ int round_up(int x, int mlt) { return (x + mlt - 1) / mlt * mlt; }
 struct dust_fluct_plan {
     int device;
     double *d_lam, *d_dlam, *d_cabs, *d_w, *d_T;
-    double *d_E, *d_eps, *d_kr, *d_cool, *d_invd;
+    double *d_E, *d_eps, *d_kr, *d_rcool, *d_invd;
     int* d_cnt;
     float* d_etab;
     dust::fluct::View view;
@@ -320,7 +374,7 @@ namespace fluct {
 void free_plan(dust_fluct_plan* p) {
     if (!p) return;
     void* ptrs[] = {p->d_lam, p->d_dlam, p->d_cabs, p->d_w, p->d_T, p->d_E,
-                    p->d_eps, p->d_kr, p->d_cool, p->d_invd, p->d_cnt, p->d_etab};
+                    p->d_eps, p->d_kr, p->d_rcool, p->d_invd, p->d_cnt, p->d_etab};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     delete p;
@@ -397,7 +451,7 @@ dust_status dust_fluct_plan_create(const dust_grid_desc* g, const dust_levels* l
     v.M = M;
     v.K = S * M;
     v.Kp = round_up(v.K, 16);
-    v.NLp = round_up(NL, 64);
+    v.NLp = round_up(NL, 128);
     v.escale = ldexpf(1.0f, ge);
     const size_t nSM = (size_t)S * M;
 #define FALLOC(ptr, n)                                                     \
@@ -413,7 +467,7 @@ dust_status dust_fluct_plan_create(const dust_grid_desc* g, const dust_levels* l
     FALLOC(p->d_E, nSM);
     FALLOC(p->d_eps, NL);
     FALLOC(p->d_kr, (size_t)S * NL);
-    FALLOC(p->d_cool, nSM);
+    FALLOC(p->d_rcool, nSM);
     FALLOC(p->d_invd, nSM);
     FALLOC(p->d_cnt, nSM * M);
     FALLOC(p->d_etab, (size_t)v.NLp * v.Kp);
@@ -435,12 +489,12 @@ dust_status dust_fluct_plan_create(const dust_grid_desc* g, const dust_levels* l
     v.eps = p->d_eps;
     v.kr = p->d_kr;
     v.E = p->d_E;
-    v.cool = p->d_cool;
+    v.rcool = p->d_rcool;
     v.invd = p->d_invd;
     v.cnt = p->d_cnt;
     v.etab = p->d_etab;
     Prep pr{v, p->d_lam, p->d_dlam, p->d_cabs, p->d_w, p->d_T,
-            p->d_eps, p->d_kr, p->d_cool, p->d_invd, p->d_cnt, p->d_etab, ge};
+            p->d_eps, p->d_kr, p->d_rcool, p->d_invd, p->d_cnt, p->d_etab, ge};
     const int64_t n_rates = (int64_t)S * NL, n_cnt = (int64_t)nSM * M,
                   n_etab = (int64_t)v.NLp * v.Kp;
     hipLaunchKernelGGL(prep_rates_kernel, dim3((unsigned)((n_rates + 255) / 256)), dim3(256), 0,
@@ -465,16 +519,17 @@ dust_status dust_fluct_plan_create(const dust_grid_desc* g, const dust_levels* l
         free_plan(p);
         return hip_error(e, "fluctuating-grain plan kernels");
     }
-    // every level above the ground must radiate (its cooling rate divides)
-    std::vector<double> cool(nSM);
-    if ((e = hipMemcpy(cool.data(), p->d_cool, sizeof(double) * nSM, hipMemcpyDeviceToHost)) !=
+    // every level above the ground must radiate (the solve multiplies by
+    // 1 / its cooling rate)
+    std::vector<double> rcool(nSM);
+    if ((e = hipMemcpy(rcool.data(), p->d_rcool, sizeof(double) * nSM, hipMemcpyDeviceToHost)) !=
         hipSuccess) {
         free_plan(p);
         return hip_error(e, "hipMemcpy (cooling rates)");
     }
     for (int s = 0; s < S; ++s)
         for (int j = 1; j < M; ++j)
-            if (!(cool[(size_t)s * M + j] > 0.0) || !isfinite(cool[(size_t)s * M + j])) {
+            if (!(rcool[(size_t)s * M + j] > 0.0) || !isfinite(rcool[(size_t)s * M + j])) {
                 free_plan(p);
                 return set_error(DUST_EINVAL,
                                  "grain " + std::to_string(s) + " level " + std::to_string(j) +
@@ -536,10 +591,15 @@ dust_status dust_fluct_emit_sed(dust_fluct_plan* p, int64_t C, const float* P, i
     if (ldp < (int64_t)v.K)
         return set_error(DUST_EINVAL, "leading dimension of P is smaller than n_grains x n_levels");
     if (ldl < v.NL) return set_error(DUST_EINVAL, "leading dimension of L is smaller than its row");
-    const int64_t blocks = (C + 15) / 16 * (v.NLp / 64);
+    const int64_t blocks = (C + 15) / 16 * (v.NLp / 128);
     if (blocks > INT32_MAX) return set_error(DUST_EUNSUPPORTED, "too many cells");
-    hipLaunchKernelGGL(emit_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, v, C,
-                       P, ldp, m, L, ldl, accumulate ? 1 : 0);
+    const bool vec = (ldp % 4) == 0 && ((uintptr_t)P & 15u) == 0 && (v.K % 4) == 0;
+    if (vec)
+        hipLaunchKernelGGL(emit_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, v, C, P, ldp, m, L, ldl, accumulate ? 1 : 0);
+    else
+        hipLaunchKernelGGL(emit_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, v, C, P, ldp, m, L, ldl, accumulate ? 1 : 0);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? DUST_OK : hip_error(e, "fluctuating-grain emission launch");
 }
