@@ -81,7 +81,11 @@ double dust_ref_guess(double lh_watt, double a_m)
     return (t < GUESS_FLOOR_K) ? GUESS_FLOOR_K : t;
 }
 
-/* Eq. 6: the heating of grain s in cell c. */
+/* Eq. 6: the heating of grain s in cell c, summed in ascending wavelength
+ * with Neumaier's compensated summation (a running correction term carries
+ * the low-order bits each addition drops, whichever operand is larger), so
+ * that the sum is correct to about one rounding whatever the spread of the
+ * terms. */
 void dust_ref_heating(int64_t n_cells, int32_t NL, int32_t S,
                       const double* J, int64_t ldj, const double* c_abs,
                       const double* dlam, double* H)
@@ -89,10 +93,15 @@ void dust_ref_heating(int64_t n_cells, int32_t NL, int32_t S,
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n_cells; ++c) {
         for (int32_t s = 0; s < S; ++s) {
-            double sum = 0.0;
-            for (int32_t l = 0; l < NL; ++l)
-                sum += J[c * ldj + l] * c_abs[(int64_t)s * NL + l] * dlam[l];
-            H[c * S + s] = sum;
+            double sum = 0.0, comp = 0.0;
+            for (int32_t l = 0; l < NL; ++l) {
+                double term = J[c * ldj + l] * c_abs[(int64_t)s * NL + l] * dlam[l];
+                double t = sum + term;
+                if (fabs(sum) >= fabs(term)) comp += (sum - t) + term;
+                else comp += (term - t) + sum;
+                sum = t;
+            }
+            H[c * S + s] = sum + comp;
         }
     }
 }

@@ -451,3 +451,25 @@ def test_reheat_first_pass_and_monotone_convergence():
     # contraction: every later increment is smaller than the one before
     assert np.all(dT[1:] <= dT[:-1] + tiny)
     assert np.all(dT[-1] < 0.6 ** 3 * dT[0] + tiny)
+
+
+def test_heating_sum_is_compensated():
+    """Eq. 6's sum keeps the low-order bits a plain running sum drops: on
+    terms spread over 16 decades it equals the correctly rounded sum
+    (math.fsum) of the same products."""
+    import math
+    rng = np.random.default_rng(5)
+    NL = 4000
+    J = np.empty((1, NL))
+    J[0, 0] = 1.0
+    J[0, 1:] = rng.uniform(0.5, 1.5, NL - 1) * 1e-16
+    c_abs = np.ones((1, NL))
+    dlam = np.ones(NL)
+    H = oracle.heating(J, c_abs, dlam)[0, 0]
+    terms = [J[0, l] * c_abs[0, l] * dlam[l] for l in range(NL)]
+    exact = math.fsum(terms)
+    naive = 0.0
+    for t in terms:
+        naive += t
+    assert abs(naive - exact) > 1e3 * abs(H - exact)  # a plain sum would not pass
+    assert H == pytest.approx(exact, rel=2e-16, abs=0)
