@@ -1,14 +1,15 @@
 // Heating, Eq. 6 (Section 4.2): H[c,s] = sum_l J[c,l] K[s,l], a dense
 // contraction over wavelength on the MFMA units.
 //
-// A workgroup computes the heating of 16 cells for every grain with the
-// LDS-staged MFMA routine of the fused kernel (fused_absorb), then writes
-// the 16 x S block of H with coalesced stores, undoing the per-grain power
-// of two.
-//   DUST_PLAIN_FP32: v_mfma_f32_16x16x4_f32 (exact FP32 products).
+//   DUST_PLAIN_FP32: a workgroup computes the heating of 16 cells for every
+//                    grain with the LDS-staged MFMA routine of the fused
+//                    kernel (fused_absorb) on v_mfma_f32_16x16x4_f32 (exact
+//                    FP32 products), then writes the 16 x S block of H with
+//                    coalesced stores, undoing the per-grain power of two.
 //   DUST_MIXED, DUST_TABLE_LINEAR:
 //                    v_mfma_f32_16x16x32_bf16 on hi+lo splits,
-//                    J_hi K_hi + J_hi K_lo + J_lo K_hi, FP32 accumulation.
+//                    J_hi K_hi + J_hi K_lo + J_lo K_hi, FP32 accumulation,
+//                    several 16-cell blocks per workgroup (absorb_mb_kernel).
 #include "fused_body.h"
 
 namespace dust {
@@ -30,17 +31,169 @@ __global__ __launch_bounds__(256) void absorb_kernel(PlanView v, int64_t C,
     }
 }
 
+// ---------------------------------------------------------------------------
+// bf16 hi+lo heating of 16 MB cells per workgroup of NW waves (MB 16-cell
+// MFMA row blocks): each wave loads the weight fragments of its grain tiles
+// (tiles wave, wave + NW, ...) once per k-step and applies them to all MB row
+// blocks, 1 / MB of the fragment traffic of one block per workgroup.  Eight
+// waves for more than four grain tiles: fewer tiles, and registers, per wave.  J goes through LDS in chunks of 16 MB
+// cells x 64 wavelengths as bf16 hi and lo planes (rows KC + 8 long, 4 banks
+// apart), double-buffered, one barrier per chunk; the accumulators go
+// straight to H.  Each product runs over every accumulator before the next
+// (consecutive MFMAs are independent), and the k-steps and the three products
+// of any one accumulator run in the order of the fused kernel's heating, so
+// H is the same bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int A_KC = 64;
+constexpr int A_ROW = A_KC + 8;
+
+// Eight-wave workgroups with up to two grain tiles per wave ask for four
+// resident waves per SIMD (two workgroups per CU; a few spilled registers):
+// 8.9 ms against 13.1 ms at two waves on 4194304 cells x 1000 x 240.
+template <int NTW, int MB, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 && NTW <= 2 ? 4 : 1, 8))) void absorb_mb_kernel(PlanView v, int64_t C,
+                                                            const float* __restrict__ J,
+                                                            int64_t ldj, float* __restrict__ H,
+                                                            int64_t ldh) {
+    constexpr int CELLS = 16 * MB;
+    constexpr int NT = 64 * NW;              // threads
+    constexpr int NX = CELLS * A_KC / NT;    // J values per thread and chunk
+    constexpr int PASSES = NX / 4;           // loader rows per thread
+    constexpr int RSTEP = NT / 16;           // rows between a thread's loader rows
+    static_assert(NX % 4 == 0 && PASSES * RSTEP == CELLS, "loader covers the chunk");
+    __shared__ __bf16 sJ[2][2][CELLS][A_ROW];  // [buffer][hi, lo][cell][wavelength]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kq = lane >> 4;
+    const int tiles = v.Sp / 16;
+    const int nsteps = v.NLp / 32;
+    const int nchunks = (nsteps + 1) / 2;  // two k-steps per chunk
+    const int64_t c0 = (int64_t)blockIdx.x * CELLS;
+    // loader: thread t takes rows (t >> 4) + RSTEP p and column pairs 2 (t mod 16) + 32 i
+    const int lrow = tid >> 4, lcol = (tid & 15) * 2;
+    auto load_j = [&](int k0, float (&x)[NX]) {
+#pragma unroll
+        for (int p = 0; p < PASSES; ++p) {
+            const int64_t c = c0 + lrow + RSTEP * p;
+            const bool ok = c < C;
+            const float* jl = J + (ok ? c : 0) * ldj;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int k = k0 + lcol + 32 * i;
+                x[4 * p + 2 * i] = (ok && k < v.NL) ? jl[k] : 0.0f;
+                x[4 * p + 2 * i + 1] = (ok && k + 1 < v.NL) ? jl[k + 1] : 0.0f;
+            }
+        }
+    };
+    auto store_j = [&](int buf, const float (&x)[NX]) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int p = 0; p < PASSES; ++p) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const float x0 = x[4 * p + 2 * i], x1 = x[4 * p + 2 * i + 1];
+                const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+                const bf16x2 hi = {h0, h1};
+                const bf16x2 lo = {(__bf16)(x0 - (float)h0), (__bf16)(x1 - (float)h1)};
+                *reinterpret_cast<bf16x2*>(&sJ[buf][0][lrow + RSTEP * p][lcol + 32 * i]) = hi;
+                *reinterpret_cast<bf16x2*>(&sJ[buf][1][lrow + RSTEP * p][lcol + 32 * i]) = lo;
+            }
+        }
+    };
+    for (int tg = 0; tg < tiles; tg += NW * NTW) {
+        f32x4 acc[NTW][MB];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float x[NX];
+        load_j(0, x);
+        store_j(0, x);
+        __syncthreads();
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < nchunks) load_j((ch + 1) * A_KC, x);  // next chunk in flight
+#pragma unroll 1
+            for (int ks = 0; ks < 2; ++ks) {
+                const int step = ch * 2 + ks;
+                if (step >= nsteps) break;  // uniform
+                bf16x8 khi[NTW], klo[NTW];
+#pragma unroll
+                for (int t = 0; t < NTW; ++t) {
+                    const int tile = tg + wave + NW * t;
+                    if (tile < tiles) {
+                        const int64_t o = (((int64_t)tile * nsteps + step) * 64 + lane) * 8;
+                        khi[t] = *reinterpret_cast<const bf16x8*>(v.khi + o);
+                        klo[t] = *reinterpret_cast<const bf16x8*>(v.klo + o);
+                    }
+                }
+                bf16x8 ahi[MB], alo[MB];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    ahi[mb] = *reinterpret_cast<const bf16x8*>(&sJ[buf][0][16 * mb + row][ks * 32 + kq * 8]);
+                    alo[mb] = *reinterpret_cast<const bf16x8*>(&sJ[buf][1][16 * mb + row][ks * 32 + kq * 8]);
+                }
+#pragma unroll
+                for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+                    for (int t = 0; t < NTW; ++t) {
+                        if (tg + wave + NW * t < tiles) {
+#pragma unroll
+                            for (int mb = 0; mb < MB; ++mb)
+                                acc[t][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    pr == 2 ? alo[mb] : ahi[mb], pr == 1 ? klo[t] : khi[t],
+                                    acc[t][mb], 0, 0, 0);
+                        }
+                    }
+            }
+            if (ch + 1 < nchunks) store_j(buf ^ 1, x);
+            __syncthreads();
+        }
+        // accumulator element r of lane (row, kq): cell 16 mb + 4 kq + r, grain 16 tile + row
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            const int tile = tg + wave + NW * t;
+            const int s = tile * 16 + row;
+            if (tile < tiles && s < v.S) {
+                const float hinv = v.hinv[s];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t c = c0 + 16 * mb + 4 * kq + r;
+                        if (c < C) H[c * ldh + s] = acc[t][mb][r] * hinv;
+                    }
+            }
+        }
+    }
+}
+
 template <int NTW>
 hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj, float* H,
                       int64_t ldh, hipStream_t st) {
+    if (table_mode(v.mode)) {  // bf16 hi+lo heating, 64 cells per workgroup
+        constexpr int MB = 4;
+        const dim3 grid((unsigned)((C + 16 * MB - 1) / (16 * MB)));
+        const int tiles = v.Sp / 16;
+        if (tiles <= 4)  // four waves, one grain tile each
+            hipLaunchKernelGGL((absorb_mb_kernel<1, MB, 4>), grid, dim3(256), 0, st, v, C, J, ldj,
+                               H, ldh);
+        else if (tiles <= 8)
+            hipLaunchKernelGGL((absorb_mb_kernel<1, MB, 8>), grid, dim3(512), 0, st, v, C, J, ldj,
+                               H, ldh);
+        else if (tiles <= 16)
+            hipLaunchKernelGGL((absorb_mb_kernel<2, MB, 8>), grid, dim3(512), 0, st, v, C, J, ldj,
+                               H, ldh);
+        else  // four tiles per wave and pass; more passes above 32 tiles
+            hipLaunchKernelGGL((absorb_mb_kernel<4, MB, 8>), grid, dim3(512), 0, st, v, C, J, ldj,
+                               H, ldh);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((C + 15) / 16));
     const size_t lds = sizeof(float) * 16 * v.Sp + STAGE_BYTES;
-    if (table_mode(v.mode))  // bf16 hi+lo heating
-        hipLaunchKernelGGL((absorb_kernel<DUST_MIXED, NTW>), grid, dim3(256), lds, st, v, C, J,
-                           ldj, H, ldh);
-    else
-        hipLaunchKernelGGL((absorb_kernel<DUST_PLAIN_FP32, NTW>), grid, dim3(256), lds, st, v, C,
-                           J, ldj, H, ldh);
+    hipLaunchKernelGGL((absorb_kernel<DUST_PLAIN_FP32, NTW>), grid, dim3(256), lds, st, v, C, J,
+                       ldj, H, ldh);
     return hipGetLastError();
 }
 

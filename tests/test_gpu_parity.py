@@ -555,3 +555,25 @@ def test_batch_matches_oracle_and_replays(dev, refresh):
         torch.cuda.synchronize()
         assert torch.equal(T1, T) and torch.equal(L1, L)
     b.close()
+
+
+@pytest.mark.parametrize("name", ["plain-262144x250x80", "full-4194304x1000x240"])
+def test_absorb_full_size_sampled(dev, name):
+    """dust_absorb (mixed heating, 64 cells per workgroup) at full size:
+    strided rows of H against the oracle's Eq. 6 on the same FP32 J."""
+    w = synth.WORKLOADS[name]
+    g = w.grid()
+    p = w.cells()
+    say(f"absorb full size {name}: generating J")
+    J = synth.radiation_field(p, g.lam, device=dev)
+    plan = dust.Plan(g, "mixed")
+    H = plan.absorb(J)
+    torch.cuda.synchronize()
+    rows = strided_rows(w.n_cells, 256)
+    idx = torch.as_tensor(rows, device=dev)
+    H_ref = oracle.heating(_host(J[idx]).astype(np.float64), g.c_abs, g.dlam)
+    pos = H_ref > 0
+    rel = np.abs(_host(H[idx]).astype(np.float64)[pos] - H_ref[pos]) / H_ref[pos]
+    say(f"absorb {name}: max rel H err {rel.max():.3g}")
+    assert rel.max() <= 1e-4
+    assert bool(torch.isfinite(H).all()) and bool((H >= 0).all())
