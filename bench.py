@@ -65,7 +65,8 @@ def source_hash(names):
     return h.hexdigest()[:16]
 
 
-FUSED_SOURCES = ["fused.hip", "fused_body.h", "device_common.h", "internal.h"]
+# the kernel sources and the build (its compiler flags change the code too)
+FUSED_SOURCES = ["fused.hip", "fused_body.h", "device_common.h", "internal.h", "../builder.py"]
 
 
 def measured_traffic(kernel_key, src_hash):
@@ -314,7 +315,7 @@ def run_reheat_leg(torch, synth, dust, grid, params, J0, m, T, L, cnt, n_passes=
     return out
 
 
-BATCH_SOURCES = ["batch.hip", "fused_body.h", "device_common.h", "internal.h"]
+BATCH_SOURCES = ["batch.hip", "fused_body.h", "device_common.h", "internal.h", "../builder.py"]
 
 
 def run_batch(args, torch, synth, dust, dev):

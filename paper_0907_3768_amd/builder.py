@@ -6,6 +6,14 @@ under measure/ become a library of their own, libdust_probe.so, which only
 the benchmark loads.  Packed FP32 instructions are disabled for the device
 code (-packed-fp32-ops): the kernels are written with ordinary scalar float
 arithmetic.
+
+Machine-level loop-invariant code motion is disabled (-disable-machine-licm):
+it hoists the constants of the tile bodies' rarely taken FP64 paths (the
+series coefficients of the exact fallback) out of the enclosing loops, where
+they hold registers for the whole tile and push the kernels that ask for six
+resident waves into spilling (the fused kernel 80 bytes per lane, the
+persistent batch kernel over a kilobyte).  Without it the fused kernels do
+not spill (the four-tile form a few registers), and measured 1-3 % faster.
 """
 from __future__ import annotations
 
@@ -36,6 +44,7 @@ def hipcc() -> str:
 def flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-disable-machine-licm",
             "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
 
 
