@@ -287,6 +287,154 @@ __global__ __launch_bounds__(64) void solve_kernel(View v, int64_t C, const floa
 }
 
 // ---------------------------------------------------------------------------
+// The same distribution for grains of at most 64 levels (one level per lane),
+// several cells of one grain per workgroup (a wave per cell).  The grain's
+// tables go through LDS once per workgroup: the photon counts as byte offsets
+// into a wave's prefix sums ([M][M] ints) and (E_i, 1 / cooling rate_i)
+// ([M] pairs).  Per level step a wave then issues only LDS reads and VALU
+// work: the lower level's value X_i = acc_i / cool_i is read from lane i of
+// the product acc * (1 / cool), its enthalpy is one broadcast LDS read, the
+// rescale test is a scalar branch on X_i's exponent word, and X is not kept
+// per level but read off the sums at the end (X_j = acc_j / cool_j, every
+// sum having taken the same rescales; X_0 = 2^(-500 rescales)).  The
+// arithmetic of every sum is the one of solve_kernel.
+// ---------------------------------------------------------------------------
+constexpr int STAGED_MAX_LEVELS = 64;
+constexpr int STAGED_MAX_WAVES = 8;
+
+// LDS of the grain's tables: the offsets [M + 1][M] (a zero row after the
+// last, read by the steps past the end), then (E, 1 / cooling rate) [M].
+__host__ __device__ inline int staged_offsets_bytes(int M) {
+    return (4 * (M + 1) * M + 15) / 16 * 16;
+}
+__host__ __device__ inline int staged_table_bytes(int M) {
+    return staged_offsets_bytes(M) + 16 * M;
+}
+
+__global__ __launch_bounds__(64 * STAGED_MAX_WAVES) void solve_staged_kernel(
+    View v, int64_t C, const float* __restrict__ J, int64_t ldj, float* __restrict__ P,
+    int64_t ldp, dust_counters* cnt) {
+    extern __shared__ __align__(16) char smem[];
+    const int NL = v.NL, M = v.M, S = v.S;
+    const int W = (int)(blockDim.x >> 6);
+    int* sOff = reinterpret_cast<int*>(smem);  // [M + 1][M] 16 * count
+    double2* sLev = reinterpret_cast<double2*>(smem + staged_offsets_bytes(M));  // [M]
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    char* sFb = smem + staged_table_bytes(M) + (size_t)wave * (NL + 1) * sizeof(double2);
+    double2* sF = reinterpret_cast<double2*>(sFb);
+    const int s = (int)(blockIdx.x % (unsigned)S);
+    const int64_t c_raw = (int64_t)(blockIdx.x / (unsigned)S) * W + wave;
+    const bool live = c_raw < C;
+    const int64_t c = live ? c_raw : C - 1;  // a wave past the end repeats the last cell, unwritten
+    // 0. the grain's tables
+    {
+        const int* cn = v.cnt + (int64_t)s * M * M;
+        for (int e = threadIdx.x; e < M * M; e += blockDim.x) sOff[e] = cn[e] * (int)sizeof(double2);
+        for (int e = threadIdx.x; e < M; e += blockDim.x) sOff[M * M + e] = 0;
+        for (int e = threadIdx.x; e < M; e += blockDim.x)
+            sLev[e] = make_double2(v.E[(int64_t)s * M + e], v.rcool[(int64_t)s * M + e]);
+    }
+    // 1. photon rates and their prefix sums, shortest wavelength first
+    const float* jr = J + c * ldj;
+    const double* kr = v.kr + (int64_t)s * NL;
+    double carry0 = 0.0, carry1 = 0.0;
+    bool bad = false;
+    if (lane == 0) sF[0] = make_double2(0.0, 0.0);
+    for (int l0 = 0; l0 < NL; l0 += 64) {
+        const int l = l0 + lane;
+        double r = 0.0, re = 0.0;
+        if (l < NL) {
+            const float jv = jr[l];
+            if (!(jv >= 0.0f) || __builtin_isinf(jv)) bad = true;
+            r = (double)jv * kr[l];
+            re = r * v.eps[l];
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double a = __shfl_up(r, d, 64), b = __shfl_up(re, d, 64);
+            if (lane >= d) {
+                r += a;
+                re += b;
+            }
+        }
+        if (l < NL) sF[l + 1] = make_double2(carry0 + r, carry1 + re);
+        carry0 += readlane_f64(r, 63);
+        carry1 += readlane_f64(re, 63);
+    }
+    const bool any_bad = __ballot(bad) != 0;
+    __syncthreads();
+    // 2. levels in order; lane j holds level j.  The LDS reads are issued
+    //    ahead of their use, so the chain from one level to the next is only
+    //    acc -> X_i -> acc: at step i the offsets of step i + 2 and the prefix
+    //    sums of step i + 1 are read, and B[j][i] is formed from the sums read
+    //    at step i - 1.  Lanes with j <= i read valid addresses and drop the
+    //    values.
+    const int j = lane;
+    const bool jok = j >= 1 && j < M;
+    const double Ejm1 = jok ? sLev[j - 1].x : 0.0;
+    const double Ej = j < M ? sLev[j].x : 0.0;
+    const double dinv = jok ? v.invd[(int64_t)s * M + j] : 0.0;
+    const double rc = j < M ? sLev[j].y : 0.0;  // 0 at j = 0
+    // offsets of step r <= M for this lane: counts of eps >= E_{j-1} - E_r and
+    // eps >= E_j - E_r, columns j - 1 and j of row r (columns 0 and 1 where
+    // the lane has no level; row M is zeros)
+    const int* col = sOff + (jok ? j - 1 : 0);
+    auto offsets = [&](int r, int& o1, int& o2) {
+        o1 = col[r * M];
+        o2 = col[r * M + 1];
+    };
+    auto sums = [&](int o) { return *reinterpret_cast<const double2*>(sFb + o); };
+    int o1, o2;
+    offsets(0, o1, o2);
+    double2 f1 = sums(o1), f2 = sums(o2);  // step 0
+    offsets(1, o1, o2);                    // step 1
+    double acc = 0.0;
+    int rescales = 0;
+    double xi = 1.0;  // X_0
+    // one step: B[j][i] from the sums (a1, a2) read at the step before, the
+    // sums of step i + 1 into (b1, b2), the offsets of step i + 2, then X_i
+    auto step = [&](int i, const double2& a1, const double2& a2, double2& b1, double2& b2) {
+        const double Ei = readlane_f64(Ej, i);
+        const double B = a2.x + ((a1.y - a2.y) - (Ejm1 - Ei) * (a1.x - a2.x)) * dinv;
+        b1 = sums(o1);
+        b2 = sums(o2);
+        offsets(i + 2, o1, o2);
+        if (i > 0) {
+            xi = readlane_f64(acc * rc, i);
+            if (__double2hiint(xi) > 0x5F2FFFFF) {  // X_i >= 2^500 (uniform): rescale, exactly
+                // (the empty asm keeps this a scalar branch: without it the
+                // compiler computes the rescale at every step and selects)
+                asm volatile("");
+                xi = ldexp(xi, -500);
+                acc = ldexp(acc, -500);
+                ++rescales;
+            }
+        }
+        if (j > i) acc = fma(B, xi, acc);
+    };
+    // two steps per pass, the sums alternating between two register sets
+    // (a copy from one to the other would wait for the reads at once)
+    double2 g1, g2;
+    int i = 0;
+    for (; i + 1 < M - 1; i += 2) {
+        step(i, f1, f2, g1, g2);
+        step(i + 1, g1, g2, f1, f2);
+    }
+    if (i < M - 1) step(i, f1, f2, g1, g2);
+    // 3. normalise
+    const double X = j == 0 ? ldexp(1.0, -500 * rescales) : (j < M ? acc * rc : 0.0);
+    const double tot = wave_sum_f64(X);
+    const double inv = 1.0 / tot;
+    if (live && j < M) {
+        const double pv = X * inv;
+        P[c * ldp + (int64_t)s * M + j] = any_bad ? __builtin_nanf("") : (float)pv;
+        if (cnt && !any_bad && j == M - 1 && pv > TOP_PROBABILITY) count(&cnt->n_out_of_table);
+    }
+    if (live && cnt && any_bad && lane == 0) count(&cnt->n_nonfinite);
+}
+
+// ---------------------------------------------------------------------------
 // Emission: a workgroup takes 16 cells x 128 wavelengths, each wave 32 of the
 // wavelengths as two 16-wide MFMA blocks that share the cells' fragment of P;
 // blocks run wavelength block fastest, so the cells' rows of P are shared in
@@ -566,6 +714,20 @@ dust_status dust_fluct_solve_P(dust_fluct_plan* p, int64_t C, const float* J, in
         return set_error(DUST_EINVAL, "leading dimension of P is smaller than n_grains x n_levels");
     const hipStream_t st = (hipStream_t)stream;
     const size_t lds = sizeof(double2) * (size_t)(v.NL + 1);
+    if (v.M <= STAGED_MAX_LEVELS) {
+        // as many cells per workgroup (up to eight) as the LDS allows
+        int w = STAGED_MAX_WAVES;
+        while (w > 1 && (size_t)staged_table_bytes(v.M) + w * lds > (size_t)MAX_LDS) w >>= 1;
+        if ((size_t)staged_table_bytes(v.M) + w * lds <= (size_t)MAX_LDS) {
+            const int64_t groups = (C + w - 1) / w;
+            hipLaunchKernelGGL(solve_staged_kernel, dim3((unsigned)(groups * v.S)), dim3(64 * w),
+                               (size_t)staged_table_bytes(v.M) + w * lds, st, v, C, J, ldj, P,
+                               ldp, cnt);
+            const hipError_t e = hipGetLastError();
+            return e == hipSuccess ? DUST_OK
+                                   : hip_error(e, "fluctuating-grain distribution launch");
+        }
+    }
     const dim3 grid((unsigned)(C * v.S));
     if (v.M <= 64)
         hipLaunchKernelGGL(solve_kernel<1>, grid, dim3(64), lds, st, v, C, J, ldj, P, ldp, cnt);
