@@ -400,9 +400,6 @@ def test_deterministic_and_prepare(dev, mode):
 
 # --------------------------------------------------------------------------- full sizes, sampled
 
-# (workload, mode, table temperatures of the mixed form; 0 = the default 1024).
-# The million-cell workload also runs with the 4096 log-spaced table
-# temperatures its configuration states.
 # (workload, mode, table temperatures of the mixed form (0 = the default
 # 1024), FP64 Newton polish).  The million-cell workload also runs as its
 # configuration states it: 4096 log-spaced table temperatures and the polish;
