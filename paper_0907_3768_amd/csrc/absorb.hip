@@ -169,9 +169,234 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8
     }
 }
 
+// ---------------------------------------------------------------------------
+// bf16 hi+lo heating as a blocked matrix product for the large shapes: a
+// workgroup of eight waves computes 256 cells x up to 16 grain tiles (256
+// grains; more grains take further passes, blockIdx.y), the weight
+// fragments of all its grain tiles and the J block of its cells staged in
+// LDS for one 32-wavelength k-step at a time, double-buffered:
+//   A (J): [buffer][hi, lo][cell][32 wavelengths + 8 pad] bf16 (80-byte rows:
+//          the 16 rows one MFMA operand read touches fall on distinct banks);
+//   B (K): [buffer][tile][hi, lo][lane] 16-byte fragments, copied from the
+//          plan's fragment order as they are.
+// Each wave holds 2 row blocks x 16 tiles of accumulators (128 registers)
+// and takes every weight fragment from LDS, so a fragment read from L2 once
+// per workgroup serves 256 cells (64 in absorb_mb_kernel).  The next k-step's
+// J values and fragments are loaded into registers during the MFMAs of the
+// current one and written to the other buffer after them; one barrier per
+// k-step.  The products of each accumulator run in the fused kernel's order
+// (k-steps ascending; hi.hi, hi.lo, lo.hi), so H is the same bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int G_CELLS = 256;
+constexpr int G_NT = 16;             // most grain tiles per pass
+constexpr int G_ROW = 40;            // bf16 per LDS row of a cell (32 + 8 pad)
+
+// NT: grain tiles of the instantiation (the pass's own count nt <= NT; the
+// MFMAs run over all NT without branches, the surplus ones on stale LDS, and
+// their accumulators are dropped).
+// VW: J load width in floats (4 or 2: rows and J aligned to it; 1 otherwise).
+template <int NT, int VW>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void absorb_gemm_kernel(
+    PlanView v, int64_t C, const float* __restrict__ J, int64_t ldj, float* __restrict__ H,
+    int64_t ldh) {
+    __shared__ __align__(16) __bf16 sA[2][2][G_CELLS][G_ROW];  // 80 KB
+    __shared__ __align__(16) bf16x8 sB[2][NT][2][64];           // up to 64 KB
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kq = lane >> 4;
+    const int t0 = (int)blockIdx.y * NT;
+    const int nt = __builtin_amdgcn_readfirstlane(min(NT, v.Sp / 16 - t0));
+    const int nsteps = v.NLp / 32;
+    const int64_t c0 = (int64_t)blockIdx.x * G_CELLS;
+    // J loader: thread t takes cell t / 2, wavelengths 16 (t mod 2) .. + 16 of a k-step
+    const int lc = tid >> 1, lk = (tid & 1) * 16;
+    const int64_t lcell = c0 + lc;
+    const float* jrow = J + (lcell < C ? lcell : 0) * ldj;
+    auto load_j = [&](int step, float (&x)[16]) {
+        const int k0 = step * 32 + lk;
+        if (lcell >= C) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = 0.0f;
+        } else if (VW == 4 && k0 + 16 <= v.NL) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 f = *reinterpret_cast<const float4*>(jrow + k0 + 4 * q);
+                x[4 * q] = f.x;
+                x[4 * q + 1] = f.y;
+                x[4 * q + 2] = f.z;
+                x[4 * q + 3] = f.w;
+            }
+        } else if (VW == 2 && k0 + 16 <= v.NL) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float2 f = *reinterpret_cast<const float2*>(jrow + k0 + 2 * q);
+                x[2 * q] = f.x;
+                x[2 * q + 1] = f.y;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = k0 + e < v.NL ? jrow[k0 + e] : 0.0f;
+        }
+    };
+    auto store_j = [&](int buf, const float (&x)[16]) {
+        bf16x8 hi[2], lo[2];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const __bf16 h = (__bf16)x[e];
+            hi[e >> 3][e & 7] = h;
+            lo[e >> 3][e & 7] = (__bf16)(x[e] - (float)h);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            *reinterpret_cast<bf16x8*>(&sA[buf][0][lc][lk + 8 * q]) = hi[q];
+            *reinterpret_cast<bf16x8*>(&sA[buf][1][lc][lk + 8 * q]) = lo[q];
+        }
+    };
+    // fragment loader: entry e = tid + 512 q: tile e / 128, plane (e / 64) mod 2, lane e mod 64
+    constexpr int KQ = (NT * 128 + 511) / 512;  // fragment entries per thread
+    auto load_k = [&](int step, bf16x8 (&y)[KQ]) {
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int e = tid + 512 * q;
+            const int t = e >> 7, pl = (e >> 6) & 1, ln = e & 63;
+            if (t < nt) {
+                const int64_t o = (((int64_t)(t0 + t) * nsteps + step) * 64 + ln) * 8;
+                y[q] = *reinterpret_cast<const bf16x8*>((pl ? v.klo : v.khi) + o);
+            }
+        }
+    };
+    auto store_k = [&](int buf, const bf16x8 (&y)[KQ]) {
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int e = tid + 512 * q;
+            const int t = e >> 7, pl = (e >> 6) & 1, ln = e & 63;
+            if (t < nt) sB[buf][t][pl][ln] = y[q];
+        }
+    };
+    // wave layout: WC cell groups x WGR grain groups; a wave takes MBW row
+    // blocks (16 MBW cells) x TW grain tiles, so each fragment read from LDS
+    // feeds 3 MBW MFMAs
+    constexpr int WGR = NT >= 8 ? 2 : 1;
+    constexpr int WC = 8 / WGR;
+    constexpr int MBW = 16 / WC;
+    constexpr int TW = NT / WGR;
+    static_assert(TW * WGR == NT, "tiles split evenly over grain groups");
+    const int cg = wave % WC, gg = wave / WC;
+    f32x4 acc[MBW][TW];
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+        for (int t = 0; t < TW; ++t) acc[mb][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float x[16];
+    bf16x8 y[KQ];
+    load_j(0, x);
+    load_k(0, y);
+    store_j(0, x);
+    store_k(0, y);
+    __syncthreads();
+    for (int step = 0; step < nsteps; ++step) {
+        const int buf = step & 1;
+        const bool more = step + 1 < nsteps;
+        if (more) {  // next k-step in flight
+            load_j(step + 1, x);
+            load_k(step + 1, y);
+        }
+        bf16x8 ahi[MBW], alo[MBW];
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb) {
+            const int cell = 16 * (MBW * cg + mb) + row;
+            ahi[mb] = *reinterpret_cast<const bf16x8*>(&sA[buf][0][cell][kq * 8]);
+            alo[mb] = *reinterpret_cast<const bf16x8*>(&sA[buf][1][cell][kq * 8]);
+        }
+        // fragments one tile ahead of their MFMAs
+        bf16x8 bhi[2], blo[2];
+        bhi[0] = sB[buf][TW * gg][0][lane];
+        blo[0] = sB[buf][TW * gg][1][lane];
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            if (t + 1 < TW) {
+                bhi[(t + 1) & 1] = sB[buf][TW * gg + t + 1][0][lane];
+                blo[(t + 1) & 1] = sB[buf][TW * gg + t + 1][1][lane];
+            }
+#pragma unroll
+            for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+                for (int mb = 0; mb < MBW; ++mb)
+                    acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        pr == 2 ? alo[mb] : ahi[mb], pr == 1 ? blo[t & 1] : bhi[t & 1],
+                        acc[mb][t], 0, 0, 0);
+        }
+        if (more) {
+            store_j(buf ^ 1, x);
+            store_k(buf ^ 1, y);
+        }
+        __syncthreads();
+    }
+    // accumulator element r of lane (row, kq): cell 16 (MBW cg + mb) + 4 kq + r,
+    // grain 16 (t0 + TW gg + t) + row
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+        const int s = 16 * (t0 + TW * gg + t) + row;
+        if (TW * gg + t < nt && s < v.S) {
+            const float hinv = v.hinv[s];
+#pragma unroll
+            for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t c = c0 + 16 * (MBW * cg + mb) + 4 * kq + r;
+                    if (c < C) H[c * ldh + s] = acc[mb][t][r] * hinv;
+                }
+        }
+    }
+}
+
+template <int NT>
+hipError_t launch_gemm(const PlanView& v, int64_t C, const float* J, int64_t ldj, float* H,
+                       int64_t ldh, hipStream_t st) {
+    const dim3 grid((unsigned)((C + G_CELLS - 1) / G_CELLS), (unsigned)((v.Sp / 16 + NT - 1) / NT));
+    const uintptr_t a = (uintptr_t)J;
+    if ((a & 15u) == 0 && (ldj & 3) == 0)
+        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 4>), grid, dim3(512), 0, st, v, C, J, ldj, H,
+                           ldh);
+    else if ((a & 7u) == 0 && (ldj & 1) == 0)
+        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 2>), grid, dim3(512), 0, st, v, C, J, ldj, H,
+                           ldh);
+    else
+        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 1>), grid, dim3(512), 0, st, v, C, J, ldj, H,
+                           ldh);
+    return hipGetLastError();
+}
+
+// Whether the current device gives one workgroup the blocked kernel's
+// 144 KB of LDS (asked once per device).
+bool gemm_fits() {
+    static int cached[64];  // 0 unknown, 1 yes, 2 no
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    if (!cached[dev]) {
+        int lds = 0;
+        (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        cached[dev] = (size_t)lds >= sizeof(__bf16) * 2 * 2 * G_CELLS * G_ROW +
+                                         sizeof(bf16x8) * 2 * G_NT * 2 * 64
+                          ? 1
+                          : 2;
+    }
+    return cached[dev] == 1;
+}
+
 template <int NTW>
 hipError_t launch_ntw(const PlanView& v, int64_t C, const float* J, int64_t ldj, float* H,
                       int64_t ldh, hipStream_t st) {
+    if (table_mode(v.mode) && gemm_fits()) {  // blocked bf16 hi+lo heating
+        const int tiles = v.Sp / 16;
+        if (tiles <= 2) return launch_gemm<2>(v, C, J, ldj, H, ldh, st);
+        if (tiles <= 4) return launch_gemm<4>(v, C, J, ldj, H, ldh, st);
+        if (tiles <= 6) return launch_gemm<6>(v, C, J, ldj, H, ldh, st);
+        if (tiles <= 8) return launch_gemm<8>(v, C, J, ldj, H, ldh, st);
+        if (tiles <= 12) return launch_gemm<12>(v, C, J, ldj, H, ldh, st);
+        return launch_gemm<16>(v, C, J, ldj, H, ldh, st);  // passes of 16 tiles
+    }
     if (table_mode(v.mode)) {  // bf16 hi+lo heating, 64 cells per workgroup
         constexpr int MB = 4;
         const dim3 grid((unsigned)((C + 16 * MB - 1) / (16 * MB)));

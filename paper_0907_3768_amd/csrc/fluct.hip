@@ -392,26 +392,37 @@ __global__ __launch_bounds__(64 * STAGED_MAX_WAVES) void solve_staged_kernel(
     double acc = 0.0;
     int rescales = 0;
     double xi = 1.0;  // X_0
+    double Ei = sLev[0].x;
     // one step: B[j][i] from the sums (a1, a2) read at the step before, the
-    // sums of step i + 1 into (b1, b2), the offsets of step i + 2, then X_i
+    // sums of step i + 1 into (b1, b2), the offsets of step i + 2 and E_{i+1},
+    // then X_i (from readlane in both branches of the rescale, so it stays in
+    // scalar registers)
     auto step = [&](int i, const double2& a1, const double2& a2, double2& b1, double2& b2) {
-        const double Ei = readlane_f64(Ej, i);
         const double B = a2.x + ((a1.y - a2.y) - (Ejm1 - Ei) * (a1.x - a2.x)) * dinv;
+        // the offsets first: LDS reads complete in order, and the next step
+        // needs them before the sums
+        int n1, n2;
+        offsets(i + 2, n1, n2);
         b1 = sums(o1);
         b2 = sums(o2);
-        offsets(i + 2, o1, o2);
+        o1 = n1;
+        o2 = n2;
+        Ei = sLev[i + 1 < M ? i + 1 : i].x;
         if (i > 0) {
             xi = readlane_f64(acc * rc, i);
             if (__double2hiint(xi) > 0x5F2FFFFF) {  // X_i >= 2^500 (uniform): rescale, exactly
                 // (the empty asm keeps this a scalar branch: without it the
                 // compiler computes the rescale at every step and selects)
                 asm volatile("");
-                xi = ldexp(xi, -500);
                 acc = ldexp(acc, -500);
                 ++rescales;
+                xi = readlane_f64(acc * rc, i);
             }
         }
-        if (j > i) acc = fma(B, xi, acc);
+        if (j > i) {
+            asm volatile("");  // (an exec-masked branch, not a select after the FMA)
+            acc = fma(B, xi, acc);
+        }
     };
     // two steps per pass, the sums alternating between two register sets
     // (a copy from one to the other would wait for the reads at once)
