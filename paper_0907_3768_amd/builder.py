@@ -41,20 +41,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def flags():
-    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-mllvm", "-disable-machine-licm",
-            "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
+def flags(licm: bool = False):
+    """Device-code flags of libdust (machine LICM off); licm=True keeps the
+    pass, for the ALU probes, whose loops must hold only the instructions
+    they time (without it the compiler rebuilds a constant in every
+    iteration of the FMA chain)."""
+    return (["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] +
+            ([] if licm else ["-mllvm", "-disable-machine-licm"]) +
+            ["-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC])
 
 
-def _compile_link(srcs, lib, objdir, extra_inc, verbose):
+def _compile_link(srcs, lib, objdir, extra_inc, verbose, licm=False):
     cc = hipcc()
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [cc] + flags() + extra_inc + ["-c", src, "-o", obj]
+        cmd = [cc] + flags(licm) + extra_inc + ["-c", src, "-o", obj]
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
         out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
         if r.returncode != 0:
@@ -81,7 +85,7 @@ def build(verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     _compile_link(srcs, LIB, os.path.join(ROOT, "_build", "obj"), [], verbose)
     _compile_link(sorted(glob.glob(os.path.join(MEASURE, "*.hip"))), PROBE_LIB,
-                  os.path.join(ROOT, "_build", "obj_probe"), ["-I", MEASURE], verbose)
+                  os.path.join(ROOT, "_build", "obj_probe"), ["-I", MEASURE], verbose, licm=True)
     return LIB
 
 
