@@ -463,6 +463,33 @@ FP32_MFMA_PEAK = 157.3e12    # MI355X dense FP32 MFMA FLOP/s
 FLUCT_WORKLOAD = "fluct-65536x250x16x64"
 
 
+# the distribution kernel's sources and the build
+FLUCT_SOURCES = ["fluct.hip", "device_common.h", "internal.h", "../builder.py"]
+
+
+def fluct_issue_figures(kernel_ms):
+    """Vector issue utilisation of the fluctuating-grain distribution kernel:
+    its FP64 and other VALU wave instructions (committed rocprofv3 --pmc
+    counts on the same sources) priced at the ALU probe's measured cycles
+    (v_fma_f64 for the FP64 ones, v_fma_f32 for the rest), over what 1024
+    SIMDs at 2.4 GHz offer in the measured duration."""
+    probe = committed_json("alu_probe.json")
+    e = (committed_json("counters.json") or {}).get("fluct_solve:" + FLUCT_WORKLOAD)
+    if not (probe and e and e.get("source_hash") == source_hash(FLUCT_SOURCES)
+            and "fma64" in probe["alu_probe"]):
+        return {"issue_frac": None}
+    cyc = {kk: vv["cycles_per_wave_step_at_2.4GHz"] for kk, vv in probe["alu_probe"].items()}
+    f64 = sum(e[n] for n in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+                             "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64"))
+    other = e["SQ_INSTS_VALU"] - f64
+    busy = f64 * cyc["fma64"] + other * cyc["fma"]
+    return {"issue_frac": busy / (N_CU * SIMD_PER_CU * CLOCK_HZ * kernel_ms * 1e-3),
+            "issue_model": ("(FP64 x %.2f + other VALU x %.2f cycles) / (1024 SIMDs x 2.4 GHz x "
+                            "duration); counts from profiles/counters.json, cycles from "
+                            "profiles/alu_probe.json" % (cyc["fma64"], cyc["fma"])),
+            "valu_per_pair": e["SQ_INSTS_VALU"] / e["pairs"]}
+
+
 def run_fluct_leg(torch, synth, dust, dev, steps, warmup, cpu_seconds=None):
     """Thermally fluctuating grains on their workload (65536 cells x 250
     wavelengths x 16 very small grains x 64 enthalpy levels): the level
@@ -494,17 +521,20 @@ def run_fluct_leg(torch, synth, dust, dev, steps, warmup, cpu_seconds=None):
     L_ref = oracle.fluct_emission(P_ref, g, lev_T, params.m_dust[rows])
     se = sed_errors(host_rows(L, rows), L_ref, g.dlam)
     pairs = C * S
+    # counted work: per pair the prefix sums (4 flops per wavelength) and the
+    # M (M - 1) / 2 level pairs of about 8 FP64 flops
     flops_solve = pairs * (8.0 * M * (M - 1) / 2 + 4.0 * NL)
     flops_emit = 2.0 * C * S * M * NL
     out = {"workload": FLUCT_WORKLOAD, "cells": C, "n_lambda": NL, "n_grains": S, "levels": M,
            "metric": "(cell,grain) level distributions/s incl. the averaged SED",
            "value": pairs / (ms * 1e-3), "ms_per_step": ms, "stages_ms": k, "steps": steps,
            "roofline": {
-               "solve_P": {"bound": "alu", "unit": "TFLOP/s (FP64 vector)",
-                           "algorithmic_flops": flops_solve,
-                           "achieved": flops_solve / (k["solve_P"] * 1e-3) / 1e12,
-                           "peak": FP64_VECTOR_PEAK / 1e12,
-                           "frac": flops_solve / (k["solve_P"] * 1e-3) / FP64_VECTOR_PEAK},
+               "solve_P": dict({"bound": "alu", "unit": "TFLOP/s (FP64 vector)",
+                                "algorithmic_flops": flops_solve,
+                                "achieved": flops_solve / (k["solve_P"] * 1e-3) / 1e12,
+                                "peak": FP64_VECTOR_PEAK / 1e12,
+                                "frac": flops_solve / (k["solve_P"] * 1e-3) / FP64_VECTOR_PEAK},
+                               **fluct_issue_figures(k["solve_P"])),
                "emit": {"bound": "mfma", "unit": "TFLOP/s (FP32 MFMA)",
                         "algorithmic_flops": flops_emit,
                         "achieved": flops_emit / (k["emit"] * 1e-3) / 1e12,
@@ -535,7 +565,7 @@ def run_fluct_leg(torch, synth, dust, dev, steps, warmup, cpu_seconds=None):
     return out
 
 
-PROBE_KINDS = (("exp2", 0), ("rcp", 1), ("fma", 2), ("exp2+fma", 3), ("term", 4))
+PROBE_KINDS = (("exp2", 0), ("rcp", 1), ("fma", 2), ("exp2+fma", 3), ("term", 4), ("fma64", 5))
 
 
 def probe_lib():
@@ -609,7 +639,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--alu-probe", action="store_true",
                     help="only run the ALU throughput probes (v_exp_f32, v_rcp_f32, v_fma_f32, "
-                         "exp + independent fma, the exact emission term) and print their rates")
+                         "exp + independent fma, the exact emission term, v_fma_f64) and print "
+                         "their rates")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline form (for kernel-trace statistics of its "
                          "kernel alone); no secondary forms and no CPU baseline")
@@ -659,7 +690,7 @@ def main():
                "config": {"workload": FLUCT_WORKLOAD, "cells": f["cells"],
                           "n_lambda": f["n_lambda"], "n_grains": f["n_grains"],
                           "levels": f["levels"], "parallelism": "single GPU"},
-               "roofline": dict(f["roofline"]["solve_P"], kernel="fluct solve_kernel<1>",
+               "roofline": dict(f["roofline"]["solve_P"], kernel="fluct solve_staged_kernel",
                                 traffic=None),
                "emit_roofline": f["roofline"]["emit"], "stages_ms": f["stages_ms"],
                "errors": f["errors"], "counters": f["counters"],

@@ -14,6 +14,8 @@
  *                       transcendental unit)
  *   ALU_PROBE_TERM      the emission's exact Planck term (mul, exp, sub, rcp,
  *                       fma)
+ *   ALU_PROBE_FMA64     v_fma_f64 (the FP64 work of the fluctuating-grain
+ *                       level recursion)
  * and writes one float per thread to the device buffer `out` (caller-owned,
  * at least 256 * blocks floats).  Returns 0 once launched on `stream` (a
  * hipStream_t; time it with events there), -1 for blocks or iters outside
@@ -33,7 +35,8 @@ enum {
     ALU_PROBE_RCP = 1,
     ALU_PROBE_FMA = 2,
     ALU_PROBE_EXP2_FMA = 3,
-    ALU_PROBE_TERM = 4
+    ALU_PROBE_TERM = 4,
+    ALU_PROBE_FMA64 = 5
 };
 
 int alu_probe_run(int32_t kind, int32_t blocks, int32_t iters, float* out, void* stream);

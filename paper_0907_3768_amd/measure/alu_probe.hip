@@ -44,9 +44,28 @@ __global__ __launch_bounds__(256) void probe_kernel(float* __restrict__ out, int
     out[gid] = s;
 }
 
+// FP64 FMA chains (same shape as the FP32 ones)
+__global__ __launch_bounds__(256) void probe_fma64_kernel(float* __restrict__ out, int iters) {
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    double x[PROBE_CHAINS];
+#pragma unroll
+    for (int i = 0; i < PROBE_CHAINS; ++i) x[i] = 0.3 + 0.01 * i + 1e-7 * (double)(gid & 1023);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < PROBE_CHAINS; ++i) x[i] = fma(x[i], 0.5, 0.25);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < PROBE_CHAINS; ++i) s += x[i];
+    out[gid] = (float)s;
+}
+
 template <int KIND>
 void launch(int blocks, int iters, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(probe_kernel<KIND>, dim3(blocks), dim3(256), 0, st, out, iters);
+    if constexpr (KIND == ALU_PROBE_FMA64)
+        hipLaunchKernelGGL(probe_fma64_kernel, dim3(blocks), dim3(256), 0, st, out, iters);
+    else
+        hipLaunchKernelGGL(probe_kernel<KIND>, dim3(blocks), dim3(256), 0, st, out, iters);
 }
 
 }  // namespace
@@ -61,6 +80,7 @@ extern "C" int alu_probe_run(int32_t kind, int32_t blocks, int32_t iters, float*
         case ALU_PROBE_FMA: launch<ALU_PROBE_FMA>(blocks, iters, out, st); break;
         case ALU_PROBE_EXP2_FMA: launch<ALU_PROBE_EXP2_FMA>(blocks, iters, out, st); break;
         case ALU_PROBE_TERM: launch<ALU_PROBE_TERM>(blocks, iters, out, st); break;
+        case ALU_PROBE_FMA64: launch<ALU_PROBE_FMA64>(blocks, iters, out, st); break;
         default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -4;

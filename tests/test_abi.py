@@ -215,7 +215,7 @@ def test_probe_constants_match_header():
     text = open(os.path.join(ROOT, "paper_0907_3768_amd", "measure", "alu_probe.h")).read()
     for name, value in bench.PROBE_KINDS:
         key = {"exp2": "EXP2", "rcp": "RCP", "fma": "FMA", "exp2+fma": "EXP2_FMA",
-               "term": "TERM"}[name]
+               "term": "TERM", "fma64": "FMA64"}[name]
         assert re.search(rf"ALU_PROBE_{key} = {value}\b", text)
 
 
