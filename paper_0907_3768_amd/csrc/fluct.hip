@@ -335,32 +335,46 @@ __global__ __launch_bounds__(64 * STAGED_MAX_WAVES) void solve_staged_kernel(
         for (int e = threadIdx.x; e < M; e += blockDim.x)
             sLev[e] = make_double2(v.E[(int64_t)s * M + e], v.rcool[(int64_t)s * M + e]);
     }
-    // 1. photon rates and their prefix sums, shortest wavelength first
+    // 1. photon rates and their prefix sums, shortest wavelength first: lane
+    //    l takes the wavelengths [l G, (l + 1) G), G = ceil(NL / 64); one
+    //    wave scan of the lanes' totals gives each lane its start, then the
+    //    lane runs through its wavelengths again writing the sums.
     const float* jr = J + c * ldj;
     const double* kr = v.kr + (int64_t)s * NL;
-    double carry0 = 0.0, carry1 = 0.0;
+    const int G = (NL + 63) >> 6;
+    const int lb = lane * G;
     bool bad = false;
-    if (lane == 0) sF[0] = make_double2(0.0, 0.0);
-    for (int l0 = 0; l0 < NL; l0 += 64) {
-        const int l = l0 + lane;
-        double r = 0.0, re = 0.0;
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = 0; q < G; ++q) {
+        const int l = lb + q;
         if (l < NL) {
             const float jv = jr[l];
             if (!(jv >= 0.0f) || __builtin_isinf(jv)) bad = true;
-            r = (double)jv * kr[l];
-            re = r * v.eps[l];
+            const double r = (double)jv * kr[l];
+            t0 += r;
+            t1 += r * v.eps[l];
         }
+    }
+    // exclusive scan of the totals: the lane below's total, then an inclusive scan
+    double e0 = __shfl_up(t0, 1, 64), e1 = __shfl_up(t1, 1, 64);
+    if (lane == 0) e0 = e1 = 0.0;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const double a = __shfl_up(r, d, 64), b = __shfl_up(re, d, 64);
-            if (lane >= d) {
-                r += a;
-                re += b;
-            }
+    for (int d = 1; d < 64; d <<= 1) {
+        const double a = __shfl_up(e0, d, 64), b = __shfl_up(e1, d, 64);
+        if (lane >= d) {
+            e0 += a;
+            e1 += b;
         }
-        if (l < NL) sF[l + 1] = make_double2(carry0 + r, carry1 + re);
-        carry0 += readlane_f64(r, 63);
-        carry1 += readlane_f64(re, 63);
+    }
+    if (lane == 0) sF[0] = make_double2(0.0, 0.0);
+    for (int q = 0; q < G; ++q) {
+        const int l = lb + q;
+        if (l < NL) {
+            const double r = (double)jr[l] * kr[l];
+            e0 += r;
+            e1 += r * v.eps[l];
+            sF[l + 1] = make_double2(e0, e1);
+        }
     }
     const bool any_bad = __ballot(bad) != 0;
     __syncthreads();
@@ -376,36 +390,40 @@ __global__ __launch_bounds__(64 * STAGED_MAX_WAVES) void solve_staged_kernel(
     const double Ej = j < M ? sLev[j].x : 0.0;
     const double dinv = jok ? v.invd[(int64_t)s * M + j] : 0.0;
     const double rc = j < M ? sLev[j].y : 0.0;  // 0 at j = 0
-    // offsets of step r <= M for this lane: counts of eps >= E_{j-1} - E_r and
-    // eps >= E_j - E_r, columns j - 1 and j of row r (columns 0 and 1 where
-    // the lane has no level; row M is zeros)
-    const int* col = sOff + (jok ? j - 1 : 0);
-    auto offsets = [&](int r, int& o1, int& o2) {
-        o1 = col[r * M];
-        o2 = col[r * M + 1];
-    };
+    // offset of step r <= M for this lane: the count of eps >= E_j - E_r
+    // (column j of row r; column M - 1 for lanes past the last level; row M
+    // is zeros).  The other bound of B[j][r], eps >= E_{j-1} - E_r, is the
+    // next lane down's: its sums come from that lane by a one-lane shift of
+    // the wave (DPP), one LDS gather per step instead of two.
+    const int* col = sOff + (j < M ? j : M - 1);
+    auto offset = [&](int r) { return col[r * M]; };
     auto sums = [&](int o) { return *reinterpret_cast<const double2*>(sFb + o); };
-    int o1, o2;
-    offsets(0, o1, o2);
-    double2 f1 = sums(o1), f2 = sums(o2);  // step 0
-    offsets(1, o1, o2);                    // step 1
+    auto from_lane_below = [](const double2& a) {
+        auto sh = [](double x) {  // lane l gets lane l - 1's x (lane 0: 0)
+            const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, false);
+            const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, false);
+            return __hiloint2double(hi, lo);
+        };
+        return make_double2(sh(a.x), sh(a.y));
+    };
+    int o2 = offset(0);
+    double2 f2 = sums(o2);  // step 0
+    o2 = offset(1);         // step 1
     double acc = 0.0;
     int rescales = 0;
     double xi = 1.0;  // X_0
     double Ei = sLev[0].x;
-    // one step: B[j][i] from the sums (a1, a2) read at the step before, the
-    // sums of step i + 1 into (b1, b2), the offsets of step i + 2 and E_{i+1},
-    // then X_i (from readlane in both branches of the rescale, so it stays in
-    // scalar registers)
-    auto step = [&](int i, const double2& a1, const double2& a2, double2& b1, double2& b2) {
+    // one step: B[j][i] from the sums a2 read at the step before (and the
+    // lane below's), the sums of step i + 1 into b2, the offset of step
+    // i + 2 and E_{i+1}, then X_i (from readlane in both branches of the
+    // rescale, so it stays in scalar registers)
+    auto step = [&](int i, const double2& a2, double2& b2) {
+        const double2 a1 = from_lane_below(a2);
         const double B = a2.x + ((a1.y - a2.y) - (Ejm1 - Ei) * (a1.x - a2.x)) * dinv;
-        // the offsets first: LDS reads complete in order, and the next step
-        // needs them before the sums
-        int n1, n2;
-        offsets(i + 2, n1, n2);
-        b1 = sums(o1);
+        // the offset first: LDS reads complete in order, and the next step
+        // needs it before the sums
+        const int n2 = offset(i + 2);
         b2 = sums(o2);
-        o1 = n1;
         o2 = n2;
         Ei = sLev[i + 1 < M ? i + 1 : i].x;
         if (i > 0) {
@@ -426,13 +444,13 @@ __global__ __launch_bounds__(64 * STAGED_MAX_WAVES) void solve_staged_kernel(
     };
     // two steps per pass, the sums alternating between two register sets
     // (a copy from one to the other would wait for the reads at once)
-    double2 g1, g2;
+    double2 g2;
     int i = 0;
     for (; i + 1 < M - 1; i += 2) {
-        step(i, f1, f2, g1, g2);
-        step(i + 1, g1, g2, f1, f2);
+        step(i, f2, g2);
+        step(i + 1, g2, f2);
     }
-    if (i < M - 1) step(i, f1, f2, g1, g2);
+    if (i < M - 1) step(i, f2, g2);
     // 3. normalise
     const double X = j == 0 ? ldexp(1.0, -500 * rescales) : (j < M ? acc * rc : 0.0);
     const double tot = wave_sum_f64(X);
