@@ -8,8 +8,12 @@
 //                    coalesced stores, undoing the per-grain power of two.
 //   DUST_MIXED, DUST_TABLE_LINEAR:
 //                    v_mfma_f32_16x16x32_bf16 on hi+lo splits,
-//                    J_hi K_hi + J_hi K_lo + J_lo K_hi, FP32 accumulation,
-//                    several 16-cell blocks per workgroup (absorb_mb_kernel).
+//                    J_hi K_hi + J_hi K_lo + J_lo K_hi, FP32 accumulation:
+//                    a blocked product of 256 cells x up to 256 grains per
+//                    workgroup with J and the weight fragments staged in LDS
+//                    (absorb_gemm_kernel), or, on a device that cannot give
+//                    one workgroup its 144 KB of LDS, 64 cells per workgroup
+//                    with the fragments read from L2 (absorb_mb_kernel).
 #include "fused_body.h"
 
 namespace dust {
@@ -179,12 +183,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8
 //          the 16 rows one MFMA operand read touches fall on distinct banks);
 //   B (K): [buffer][tile][hi, lo][lane] 16-byte fragments, copied from the
 //          plan's fragment order as they are.
-// Each wave holds 2 row blocks x 16 tiles of accumulators (128 registers)
-// and takes every weight fragment from LDS, so a fragment read from L2 once
-// per workgroup serves 256 cells (64 in absorb_mb_kernel).  The next k-step's
-// J values and fragments are loaded into registers during the MFMAs of the
+// With eight or more tiles the waves split into four cell groups of 64 x two
+// grain groups, each holding 4 row blocks x NT/2 tiles of accumulators (128
+// registers at 16 tiles), so each fragment read from LDS feeds 12 MFMAs;
+// fewer tiles: eight cell groups of 32.  A fragment read from L2 once per
+// workgroup serves 256 cells (64 in absorb_mb_kernel).  The next k-step's J
+// values and fragments are loaded into registers during the MFMAs of the
 // current one and written to the other buffer after them; one barrier per
-// k-step.  The products of each accumulator run in the fused kernel's order
+// k-step; each tile's fragments are read from LDS one tile ahead of its
+// MFMAs.  The products of each accumulator run in the fused kernel's order
 // (k-steps ascending; hi.hi, hi.lo, lo.hi), so H is the same bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int G_CELLS = 256;
