@@ -175,7 +175,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8
 
 // ---------------------------------------------------------------------------
 // bf16 hi+lo heating as a blocked matrix product for the large shapes: a
-// workgroup of eight waves computes 256 cells x up to 16 grain tiles (256
+// workgroup of sixteen waves computes 256 cells x up to 16 grain tiles (256
 // grains; more grains take further passes, blockIdx.y), the weight
 // fragments of all its grain tiles and the J block of its cells staged in
 // LDS for one 32-wavelength k-step at a time, double-buffered:
@@ -183,11 +183,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8
 //          the 16 rows one MFMA operand read touches fall on distinct banks);
 //   B (K): [buffer][tile][hi, lo][lane] 16-byte fragments, copied from the
 //          plan's fragment order as they are.
-// With eight or more tiles the waves split into four cell groups of 64 x two
-// grain groups, each holding 4 row blocks x NT/2 tiles of accumulators (128
-// registers at 16 tiles), so each fragment read from LDS feeds 12 MFMAs;
-// fewer tiles: eight cell groups of 32.  A fragment read from L2 once per
-// workgroup serves 256 cells (64 in absorb_mb_kernel).  The next k-step's J
+// Sixteen waves, four per SIMD: with eight or more tiles they split into eight
+// cell groups of 32 x two grain groups, each holding 2 row blocks x NT/2
+// tiles of accumulators (64 registers at 16 tiles, 120 in all), so each
+// fragment read from LDS feeds 6 MFMAs; fewer tiles: sixteen cell groups of
+// 16.  (Eight waves of 64 cells x 8 tiles, 12 MFMAs per fragment read but two
+// waves per SIMD, measured 12-18 % slower: the four waves per SIMD cover the
+// LDS and barrier latencies.)  A fragment read from L2 once per workgroup
+// serves 256 cells (64 in absorb_mb_kernel).  The next k-step's J
 // values and fragments are loaded into registers during the MFMAs of the
 // current one and written to the other buffer after them; one barrier per
 // k-step; each tile's fragments are read from LDS one tile ahead of its
@@ -197,13 +200,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8
 constexpr int G_CELLS = 256;
 constexpr int G_NT = 16;             // most grain tiles per pass
 constexpr int G_ROW = 40;            // bf16 per LDS row of a cell (32 + 8 pad)
+constexpr int GW = 16;               // waves per workgroup (four per SIMD)
 
 // NT: grain tiles of the instantiation (the pass's own count nt <= NT; the
 // MFMAs run over all NT without branches, the surplus ones on stale LDS, and
 // their accumulators are dropped).
 // VW: J load width in floats (4 or 2: rows and J aligned to it; 1 otherwise).
 template <int NT, int VW>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void absorb_gemm_kernel(
+__global__ __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GW / 4, GW / 4))) void absorb_gemm_kernel(
     PlanView v, int64_t C, const float* __restrict__ J, int64_t ldj, float* __restrict__ H,
     int64_t ldh) {
     __shared__ __align__(16) __bf16 sA[2][2][G_CELLS][G_ROW];  // 80 KB
@@ -216,56 +220,59 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int nt = __builtin_amdgcn_readfirstlane(min(NT, v.Sp / 16 - t0));
     const int nsteps = v.NLp / 32;
     const int64_t c0 = (int64_t)blockIdx.x * G_CELLS;
-    // J loader: thread t takes cell t / 2, wavelengths 16 (t mod 2) .. + 16 of a k-step
-    const int lc = tid >> 1, lk = (tid & 1) * 16;
+    // J loader: thread t takes cell t / TPR, wavelengths PER (t mod TPR) .. + PER of a k-step
+    constexpr int NTH = 64 * GW;
+    constexpr int PER = G_CELLS * 32 / NTH;   // J values per thread and step
+    constexpr int TPR = 32 / PER;             // threads per cell row
+    const int lc = tid / TPR, lk = (tid % TPR) * PER;
     const int64_t lcell = c0 + lc;
     const float* jrow = J + (lcell < C ? lcell : 0) * ldj;
-    auto load_j = [&](int step, float (&x)[16]) {
+    auto load_j = [&](int step, float (&x)[PER]) {
         const int k0 = step * 32 + lk;
         if (lcell >= C) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) x[e] = 0.0f;
-        } else if (VW == 4 && k0 + 16 <= v.NL) {
+            for (int e = 0; e < PER; ++e) x[e] = 0.0f;
+        } else if (VW == 4 && k0 + PER <= v.NL) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < PER / 4; ++q) {
                 const float4 f = *reinterpret_cast<const float4*>(jrow + k0 + 4 * q);
                 x[4 * q] = f.x;
                 x[4 * q + 1] = f.y;
                 x[4 * q + 2] = f.z;
                 x[4 * q + 3] = f.w;
             }
-        } else if (VW == 2 && k0 + 16 <= v.NL) {
+        } else if (VW == 2 && k0 + PER <= v.NL) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < PER / 2; ++q) {
                 const float2 f = *reinterpret_cast<const float2*>(jrow + k0 + 2 * q);
                 x[2 * q] = f.x;
                 x[2 * q + 1] = f.y;
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) x[e] = k0 + e < v.NL ? jrow[k0 + e] : 0.0f;
+            for (int e = 0; e < PER; ++e) x[e] = k0 + e < v.NL ? jrow[k0 + e] : 0.0f;
         }
     };
-    auto store_j = [&](int buf, const float (&x)[16]) {
-        bf16x8 hi[2], lo[2];
+    auto store_j = [&](int buf, const float (&x)[PER]) {
+        bf16x8 hi[PER / 8], lo[PER / 8];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < PER; ++e) {
             const __bf16 h = (__bf16)x[e];
             hi[e >> 3][e & 7] = h;
             lo[e >> 3][e & 7] = (__bf16)(x[e] - (float)h);
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < PER / 8; ++q) {
             *reinterpret_cast<bf16x8*>(&sA[buf][0][lc][lk + 8 * q]) = hi[q];
             *reinterpret_cast<bf16x8*>(&sA[buf][1][lc][lk + 8 * q]) = lo[q];
         }
     };
-    // fragment loader: entry e = tid + 512 q: tile e / 128, plane (e / 64) mod 2, lane e mod 64
-    constexpr int KQ = (NT * 128 + 511) / 512;  // fragment entries per thread
+    // fragment loader: entry e = tid + NTH q: tile e / 128, plane (e / 64) mod 2, lane e mod 64
+    constexpr int KQ = (NT * 128 + NTH - 1) / NTH;  // fragment entries per thread
     auto load_k = [&](int step, bf16x8 (&y)[KQ]) {
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
-            const int e = tid + 512 * q;
+            const int e = tid + NTH * q;
             const int t = e >> 7, pl = (e >> 6) & 1, ln = e & 63;
             if (t < nt) {
                 const int64_t o = (((int64_t)(t0 + t) * nsteps + step) * 64 + ln) * 8;
@@ -276,7 +283,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     auto store_k = [&](int buf, const bf16x8 (&y)[KQ]) {
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
-            const int e = tid + 512 * q;
+            const int e = tid + NTH * q;
             const int t = e >> 7, pl = (e >> 6) & 1, ln = e & 63;
             if (t < nt) sB[buf][t][pl][ln] = y[q];
         }
@@ -285,7 +292,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // blocks (16 MBW cells) x TW grain tiles, so each fragment read from LDS
     // feeds 3 MBW MFMAs
     constexpr int WGR = NT >= 8 ? 2 : 1;
-    constexpr int WC = 8 / WGR;
+    constexpr int WC = GW / WGR;
     constexpr int MBW = 16 / WC;
     constexpr int TW = NT / WGR;
     static_assert(TW * WGR == NT, "tiles split evenly over grain groups");
@@ -295,7 +302,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
         for (int t = 0; t < TW; ++t) acc[mb][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float x[16];
+    float x[PER];
     bf16x8 y[KQ];
     load_j(0, x);
     load_k(0, y);
@@ -364,13 +371,13 @@ hipError_t launch_gemm(const PlanView& v, int64_t C, const float* J, int64_t ldj
     const dim3 grid((unsigned)((C + G_CELLS - 1) / G_CELLS), (unsigned)((v.Sp / 16 + NT - 1) / NT));
     const uintptr_t a = (uintptr_t)J;
     if ((a & 15u) == 0 && (ldj & 3) == 0)
-        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 4>), grid, dim3(512), 0, st, v, C, J, ldj, H,
+        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 4>), grid, dim3(64 * GW), 0, st, v, C, J, ldj, H,
                            ldh);
     else if ((a & 7u) == 0 && (ldj & 1) == 0)
-        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 2>), grid, dim3(512), 0, st, v, C, J, ldj, H,
+        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 2>), grid, dim3(64 * GW), 0, st, v, C, J, ldj, H,
                            ldh);
     else
-        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 1>), grid, dim3(512), 0, st, v, C, J, ldj, H,
+        hipLaunchKernelGGL((absorb_gemm_kernel<NT, 1>), grid, dim3(64 * GW), 0, st, v, C, J, ldj, H,
                            ldh);
     return hipGetLastError();
 }
