@@ -44,14 +44,14 @@ constexpr double TOP_PROBABILITY = 1e-6;  // counted when the top level holds mo
 
 struct View {
     int NL, S, M;
-    int K, Kp, NLp;       // K = S M; Kp = K rounded up to 16; NLp = NL rounded up to 128
+    int K, Kp, NLp;       // K = S M; Kp = K rounded up to 32; NLp = NL rounded up to 128
     const double* eps;    // [NL] photon energies h c / lam (J)
     const double* kr;     // [S][NL] C dlam / eps: J times it is the photon rate
     const double* E;      // [S][M] level enthalpies
     const double* rcool;  // [S][M] (E_j - E_{j-1}) / P(T_j): 1 / the cooling rate, 0 at j = 0
     const double* invd;   // [S][M] 1 / (E_j - E_{j-1}), 0 at j = 0
     const int* cnt;       // [S][M][M] cnt[s][i][k] = #{l : eps_l >= E_k - E_i} (NL for k <= i)
-    const float* etab;    // [NLp][Kp] w_s C[s,l] B(lam_l, T_sj) 2^-ge, zero padded
+    const float* etab;    // [Kp][NLp] w_s C[s,l] B(lam_l, T_sj) 2^-ge, zero padded
     float escale;         // 2^ge
 };
 
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void prep_etab_kernel(Prep p) {
     const View& v = p.v;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= (int64_t)v.NLp * v.Kp) return;
-    const int l = (int)(t / v.Kp), k = (int)(t - (int64_t)l * v.Kp);
+    const int k = (int)(t / v.NLp), l = (int)(t - (int64_t)k * v.NLp);
     float val = 0.0f;
     if (l < v.NL && k < v.K) {
         const int s = k / v.M;
@@ -464,66 +464,117 @@ __global__ __launch_bounds__(64 * STAGED_MAX_WAVES) void solve_staged_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Emission: a workgroup takes 16 cells x 128 wavelengths, each wave 32 of the
-// wavelengths as two 16-wide MFMA blocks that share the cells' fragment of P;
-// blocks run wavelength block fastest, so the cells' rows of P are shared in
-// L2 by consecutive workgroups.  MFMA i of a 16-wide k step takes
-// k = k0 + 4 q + i in slot q of both operands (lane = 16 q + row).  VEC: P's
-// rows are 16-byte aligned and K is a multiple of 4, so a lane's four k of a
-// step are one float4.
+// Emission: L[c,l] = m_c sum_k P[c,k] Etab[k,l] on v_mfma_f32_16x16x4_f32.  A
+// workgroup of four waves takes 64 cells x 128 wavelengths, each wave 16
+// cells x all 128 (eight 16x16 accumulator blocks sharing the cells' P
+// values).  The table goes through LDS in chunks of 32 k x 128 wavelengths,
+// double-buffered, rows of 130 floats (the four k-rows one B read touches fall
+// on distinct bank groups); the next chunk and the next P values load during
+// the MFMAs of the current one.  Within a chunk MFMA sub-step s takes, in
+// k-slot q (lane = 16 q + row), the k = k0 + 8 q + s: one permutation of the
+// chunk's k for both operands, so a lane's eight P values of a chunk are
+// consecutive.  VW: P load width in floats (rows and P aligned to it).
 // ---------------------------------------------------------------------------
-template <bool VEC>
+constexpr int E_KC = 32;
+constexpr int E_ROW = 130;
+constexpr int E_CELLS = 64;
+
+template <int VW>
 __global__ __launch_bounds__(256) void emit_kernel(View v, int64_t C, const float* __restrict__ P,
                                                    int64_t ldp, const float* __restrict__ m,
                                                    float* __restrict__ L, int64_t ldl,
                                                    int accumulate) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ __align__(16) float sE[2][E_KC][E_ROW];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 15, q = lane >> 4;
     const int nlb = v.NLp / 128;
     const int64_t b = blockIdx.x;
     const int lb = (int)(b % nlb);
-    const int64_t c0 = (b / nlb) * 16;
-    const int row = lane & 15, q = lane >> 4;
-    const int l0 = lb * 128 + wave * 32;  // this wave: wavelengths l0 + row and l0 + 16 + row
+    const int64_t c0 = (b / nlb) * E_CELLS + 16 * wave;
+    const int l0 = lb * 128;
     const int64_t cr = c0 + row;
     const bool c_ok = cr < C;
     const float* pr = P + (c_ok ? cr : 0) * ldp;
-    const float* e0 = v.etab + (int64_t)(l0 + row) * v.Kp;
-    const float* e1 = e0 + (int64_t)16 * v.Kp;
-    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
-#pragma unroll 2
-    for (int k0 = 0; k0 < v.K; k0 += 16) {
-        const int kq = k0 + 4 * q;
-        float4 a;
-        if constexpr (VEC) {
-            a = (c_ok && kq < v.K) ? *reinterpret_cast<const float4*>(pr + kq)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
-        } else {
-            a.x = (c_ok && kq < v.K) ? pr[kq] : 0.0f;
-            a.y = (c_ok && kq + 1 < v.K) ? pr[kq + 1] : 0.0f;
-            a.z = (c_ok && kq + 2 < v.K) ? pr[kq + 2] : 0.0f;
-            a.w = (c_ok && kq + 3 < v.K) ? pr[kq + 3] : 0.0f;
+    const int nch = v.Kp / E_KC;
+    // table loader: thread t takes k-row t / 8 of the chunk, wavelengths 16 (t mod 8) .. + 16
+    const int ek = tid >> 3, el = (tid & 7) * 16;
+    auto load_e = [&](int ch, float4 (&e)[4]) {
+        const float* src = v.etab + (int64_t)(ch * E_KC + ek) * v.NLp + l0 + el;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = *reinterpret_cast<const float4*>(src + 4 * i);
+    };
+    auto store_e = [&](int buf, const float4 (&e)[4]) {
+        float* dst = &sE[buf][ek][el];  // 8-byte aligned (rows of 520 bytes)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            *reinterpret_cast<float2*>(dst + 4 * i) = make_float2(e[i].x, e[i].y);
+            *reinterpret_cast<float2*>(dst + 4 * i + 2) = make_float2(e[i].z, e[i].w);
         }
-        const float4 x0 = *reinterpret_cast<const float4*>(e0 + kq);
-        const float4 x1 = *reinterpret_cast<const float4*>(e1 + kq);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x0.x, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, x1.x, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x0.y, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, x1.y, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, x0.z, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, x1.z, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, x0.w, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, x1.w, acc1, 0, 0, 0);
+    };
+    auto load_p = [&](int ch, float (&a)[8]) {
+        const int k = ch * E_KC + 8 * q;
+        if (VW == 4 && c_ok && k + 8 <= v.K) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const float4 f = *reinterpret_cast<const float4*>(pr + k + 4 * i);
+                a[4 * i] = f.x;
+                a[4 * i + 1] = f.y;
+                a[4 * i + 2] = f.z;
+                a[4 * i + 3] = f.w;
+            }
+        } else if (VW == 2 && c_ok && k + 8 <= v.K) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float2 f = *reinterpret_cast<const float2*>(pr + k + 2 * i);
+                a[2 * i] = f.x;
+                a[2 * i + 1] = f.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = (c_ok && k + i < v.K) ? pr[k + i] : 0.0f;
+        }
+    };
+    f32x4 acc[8];
+#pragma unroll
+    for (int blk = 0; blk < 8; ++blk) acc[blk] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float4 e[4];
+    float a[8], an[8];
+    load_e(0, e);
+    load_p(0, a);
+    store_e(0, e);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        const bool more = ch + 1 < nch;
+        if (more) {
+            load_e(ch + 1, e);
+            load_p(ch + 1, an);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int blk = 0; blk < 8; ++blk)
+                acc[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], sE[buf][8 * q + s][16 * blk + row],
+                                                                acc[blk], 0, 0, 0);
+        if (more) {
+            store_e(buf ^ 1, e);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = an[i];
+        }
+        __syncthreads();
     }
+    // accumulator element r of lane (row, q): cell c0 + 4 q + r, wavelength l0 + 16 blk + row
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int64_t cc = c0 + 4 * q + r;
         if (cc >= C) continue;
         const float scale = (m ? m[cc] : 1.0f) * v.escale;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int l = l0 + 16 * h + row;
+        for (int blk = 0; blk < 8; ++blk) {
+            const int l = l0 + 16 * blk + row;
             if (l < v.NL) {
-                const float val = (h ? acc1[r] : acc0[r]) * scale;
+                const float val = acc[blk][r] * scale;
                 float* dst = L + cc * ldl + l;
                 *dst = accumulate ? *dst + val : val;
             }
@@ -627,7 +678,7 @@ dust_status dust_fluct_plan_create(const dust_grid_desc* g, const dust_levels* l
     v.S = S;
     v.M = M;
     v.K = S * M;
-    v.Kp = round_up(v.K, 16);
+    v.Kp = round_up(v.K, 32);
     v.NLp = round_up(NL, 128);
     v.escale = ldexpf(1.0f, ge);
     const size_t nSM = (size_t)S * M;
@@ -782,15 +833,19 @@ dust_status dust_fluct_emit_sed(dust_fluct_plan* p, int64_t C, const float* P, i
     if (ldp < (int64_t)v.K)
         return set_error(DUST_EINVAL, "leading dimension of P is smaller than n_grains x n_levels");
     if (ldl < v.NL) return set_error(DUST_EINVAL, "leading dimension of L is smaller than its row");
-    const int64_t blocks = (C + 15) / 16 * (v.NLp / 128);
+    const int64_t blocks = (C + E_CELLS - 1) / E_CELLS * (v.NLp / 128);
     if (blocks > INT32_MAX) return set_error(DUST_EUNSUPPORTED, "too many cells");
-    const bool vec = (ldp % 4) == 0 && ((uintptr_t)P & 15u) == 0 && (v.K % 4) == 0;
-    if (vec)
-        hipLaunchKernelGGL(emit_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
-                           (hipStream_t)stream, v, C, P, ldp, m, L, ldl, accumulate ? 1 : 0);
+    const hipStream_t st = (hipStream_t)stream;
+    const int acc_flag = accumulate ? 1 : 0;
+    if ((ldp % 4) == 0 && ((uintptr_t)P & 15u) == 0)
+        hipLaunchKernelGGL(emit_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, v, C, P, ldp,
+                           m, L, ldl, acc_flag);
+    else if ((ldp % 2) == 0 && ((uintptr_t)P & 7u) == 0)
+        hipLaunchKernelGGL(emit_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, v, C, P, ldp,
+                           m, L, ldl, acc_flag);
     else
-        hipLaunchKernelGGL(emit_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
-                           (hipStream_t)stream, v, C, P, ldp, m, L, ldl, accumulate ? 1 : 0);
+        hipLaunchKernelGGL(emit_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, v, C, P, ldp,
+                           m, L, ldl, acc_flag);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? DUST_OK : hip_error(e, "fluctuating-grain emission launch");
 }
