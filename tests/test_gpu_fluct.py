@@ -196,3 +196,27 @@ def test_fluct_workload_sampled(dev):
     assert torch.allclose(sums, torch.ones_like(sums), rtol=0, atol=1e-5)
     assert bool(torch.isfinite(L).all())
     assert int(_host(cnt)[0]) == 0
+
+
+@pytest.mark.parametrize("pad", [0, 2, 1])
+def test_emission_load_widths(dev, pad):
+    """dust_fluct_emit_sed with P rows of S M + pad floats: float4 loads
+    (pad 0, S M a multiple of 4), float2 (pad 2), single floats (pad 1);
+    70 cells (a ragged last workgroup of 64), 200 wavelengths (a ragged last
+    block of 128) and 5 x 12 grain-levels (a ragged last 32-k chunk)."""
+    g, lev_T, lev_E, p, J, m = _case(dev, 70, 200, [2], 5, 12, 77)
+    plan = dust.FluctPlan(g, lev_T, lev_E)
+    K = g.n_grains * 12
+    Pbuf = torch.full((70, K + pad), -2.0, dtype=torch.float32, device=dev)
+    P = Pbuf[:, :K]
+    plan.solve_P(J, P)
+    Lbuf = torch.full((70, 200 + 3), -3.0, dtype=torch.float32, device=dev)
+    L = Lbuf[:, :200]
+    plan.emit(P, m, L)
+    torch.cuda.synchronize()
+    assert torch.all(Lbuf[:, 200:] == -3.0)
+    P_ref = oracle.fluct_distribution(_host(J).astype(np.float64), g, lev_T, lev_E)
+    _check_P(_host(P).reshape(70, g.n_grains, 12), P_ref)
+    se = sed_errors(_host(L), oracle.fluct_emission(P_ref, g, lev_T, p.m_dust), g.dlam)
+    say(f"fluct emission pad={pad}: SED {se}")
+    assert se["max"] <= SED_TOL and se["energy_l1"] <= SED_TOL

@@ -556,8 +556,8 @@ def test_batch_matches_oracle_and_replays(dev, refresh):
 
 @pytest.mark.parametrize("name", ["plain-262144x250x80", "full-4194304x1000x240"])
 def test_absorb_full_size_sampled(dev, name):
-    """dust_absorb (mixed heating, 64 cells per workgroup) at full size:
-    strided rows of H against the oracle's Eq. 6 on the same FP32 J."""
+    """dust_absorb (mixed heating, the blocked kernel) at full size: strided
+    rows of H against the oracle's Eq. 6 on the same FP32 J."""
     w = synth.WORKLOADS[name]
     g = w.grid()
     p = w.cells()
@@ -574,3 +574,39 @@ def test_absorb_full_size_sampled(dev, name):
     say(f"absorb {name}: max rel H err {rel.max():.3g}")
     assert rel.max() <= 1e-4
     assert bool(torch.isfinite(H).all()) and bool((H >= 0).all())
+
+
+# (cells, wavelengths, species, sizes per species, row length of J, J's
+# offset in floats).  The blocked heating kernel's load widths (4 floats: row
+# length and start 16-byte aligned; 2: 8-byte aligned; 1: neither), ragged cell
+# and wavelength counts, and grain counts of one to four passes of 16 tiles.
+ABSORB_SHAPES = [(257, 100, [0], 5, 100, 0),       # float4 rows, 5 grains, 257 cells
+                 (300, 250, [0, 1], 40, 250, 0),   # float2 rows (the 262k-cell shape)
+                 (515, 250, [0, 1], 40, 253, 0),   # odd rows: scalar loads
+                 (129, 200, [0, 1], 40, 204, 2),   # rows aligned to 8 bytes only
+                 (70, 64, [0, 1, 2], 100, 64, 0),  # 300 grains: two passes (16 + 3 tiles)
+                 (40, 96, [0, 1], 512, 96, 0)]     # 1024 grains: four passes
+
+
+@pytest.mark.parametrize("n_cells,n_lambda,species,n_sizes,ldj,off", ABSORB_SHAPES)
+def test_absorb_load_widths_and_passes(dev, n_cells, n_lambda, species, n_sizes, ldj, off):
+    """dust_absorb in the mixed form against the oracle's Eq. 6 on every row,
+    H written to padded rows (the padding untouched)."""
+    g = synth.make_species_grid(n_lambda, species, n_sizes)
+    say(f"absorb C={n_cells} NL={n_lambda} S={g.n_grains} ldj={ldj} off={off}")
+    p = synth.cell_params(n_cells, 700 + n_cells)
+    buf = torch.full((n_cells * ldj + off + 8,), -7.0, dtype=torch.float32, device=dev)
+    J = buf[off:off + n_cells * ldj].view(n_cells, ldj)[:, :n_lambda]
+    synth.radiation_field(p, g.lam, device=dev, out=J)
+    plan = dust.Plan(g, "mixed")
+    Hbuf = torch.full((n_cells, g.n_grains + 3), -5.0, dtype=torch.float32, device=dev)
+    H = Hbuf[:, :g.n_grains]
+    plan.absorb(J, H)
+    torch.cuda.synchronize()
+    assert torch.all(Hbuf[:, g.n_grains:] == -5.0)
+    H_ref = oracle.heating(_host(J).astype(np.float64), g.c_abs, g.dlam)
+    pos = H_ref > 0
+    rel = np.abs(_host(H).astype(np.float64)[pos] - H_ref[pos]) / H_ref[pos]
+    say(f"  max rel H err {rel.max():.3g}")
+    assert rel.max() <= 1e-4
+    assert np.all(_host(H)[~pos] == 0.0)
