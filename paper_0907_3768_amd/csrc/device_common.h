@@ -267,8 +267,10 @@ __device__ inline float solve_newton_wave(const float* __restrict__ kb,
 // Taylor series to r^12 (truncation < 2e-16 relative), then 2^k.  Overflow
 // gives +inf, underflow 0 (through subnormals).
 // ---------------------------------------------------------------------------
+constexpr double EXP_F64_OVERFLOW = 709.782712893384;  // ln of the largest double
+
 __device__ __forceinline__ double exp_f64(double x) {
-    if (x > 709.782712893384) return __builtin_inf();
+    if (x > EXP_F64_OVERFLOW) return __builtin_inf();
     if (x < -745.1332191019412) return 0.0;
     const double k = __builtin_rint(x * 1.4426950408889634);
     double r = fma(-k, 6.93147180369123816490e-01, x);
@@ -305,7 +307,10 @@ __device__ __forceinline__ double expm1_pos(double x) {
 // Exact FP64 power of grain s at T and T dP/dT (Eq. 7's right side), summed
 // over wavelengths by the whole wave: lane i takes wavelengths i, i+64, ...;
 // a butterfly reduction leaves both totals in every lane.  Every lane of the
-// wave must call it with the same (s, T).
+// wave must call it with the same (s, T).  The wavelengths increase, so x =
+// c2 / (lam T) falls with l: a 64-wavelength chunk whose last x is past the
+// overflow point of e^x holds only exact zero terms and is skipped (cold
+// grains skip the short half of the grid; the sums are unchanged bit for bit).
 // ---------------------------------------------------------------------------
 __device__ inline void wave_power_f64(const PlanView& v, int s, double T, double* P, double* D) {
     const int lane = threadIdx.x & 63;
@@ -313,13 +318,18 @@ __device__ inline void wave_power_f64(const PlanView& v, int s, double T, double
     const double invT = rcp_f64(T);
     double p = 0.0, d = 0.0;
 #pragma unroll 1
-    for (int l = lane; l < v.NL; l += 64) {
-        const double x = v.c2l[l] * invT;
-        const double em = expm1_pos(x);
-        const double r = (em < __builtin_inf()) ? rcp_f64(em) : 0.0;  // 0 once e^x overflows
-        const double b = kdb[l] * r;
-        p += b;
-        d += b * x * (1.0 + r);
+    for (int l0 = 0; l0 < v.NL; l0 += 64) {
+        const int last = (l0 + 63 < v.NL) ? l0 + 63 : v.NL - 1;
+        if (v.c2l[last] * invT > EXP_F64_OVERFLOW) continue;  // every e^x overflows
+        const int l = l0 + lane;
+        if (l < v.NL) {
+            const double x = v.c2l[l] * invT;
+            const double em = expm1_pos(x);
+            const double r = (em < __builtin_inf()) ? rcp_f64(em) : 0.0;  // 0 once e^x overflows
+            const double b = kdb[l] * r;
+            p += b;
+            d += b * x * (1.0 + r);
+        }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -349,7 +359,8 @@ __device__ inline double wave_solve_exact_f64(const PlanView& v, int s, double h
             const double r = ln_f32_value(P, v.lntab) - lnH;
             if (r < 0.0) lo = lnT; else hi = lnT;
             next = lnT - r * P / D;
-            if (fabs(next - lnT) <= 1e-14) { *ok = true; return next; }
+            // a step below 1e-9 leaves an error near its square: done
+            if (fabs(next - lnT) <= 1e-9) { *ok = true; return next; }
             if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
         }
         if (hi - lo <= 1e-14) { *ok = true; return 0.5 * (lo + hi); }
@@ -533,7 +544,8 @@ __device__ __forceinline__ int mixed_lookup(const PlanView& v, int s, float hs, 
 // Bracket [*lo, *hi] and start *lnT0 (ln T) of the exact solve of a pair
 // the table lookup did not take, y = ln H': below the table (T < T_0), above
 // it, a grain whose table is not finite, or a pair on the table's edge that
-// FP32 rounding put outside.  Starts extrapolate the end interval's slope.
+// FP32 rounding put outside.  Starts extrapolate the end interval's slope
+// (in 1/T below the table, in ln T above it).
 __device__ inline void pending_bracket(const PlanView& v, int s, double y, double* lo,
                                        double* hi, double* lnT0) {
     const double ylo = v.ylo[s], yhi = v.yhi[s];
@@ -545,8 +557,12 @@ __device__ inline void pending_bracket(const PlanView& v, int s, double y, doubl
     if (!(__builtin_isfinite(ylo) && __builtin_isfinite(yhi) && yhi > ylo)) {
         *lnT0 = 0.5 * (*lo + *hi);
     } else if (y < ylo) {
+        // Wien side: ln P' is close to linear in 1/T there, so extrapolate the
+        // first interval's slope in u = 1/T (one Newton step fewer below 1.5 K)
         *hi = v.lnTmin;
-        *lnT0 = v.lnTmin + (y - ylo) * v.hstep / (f[1] - f[0]);
+        const double u0 = exp_f64(-v.lnTmin), u1 = exp_f64(-(v.lnTmin + v.hstep));
+        const double u = u0 + (y - ylo) * (u1 - u0) / (f[1] - f[0]);
+        *lnT0 = (u > u0 && u < 1e300) ? -ln_f32_value(u, v.lntab) : 0.5 * (*lo + *hi);
     } else if (y > yhi) {
         *lo = lnTmax;
         *lnT0 = lnTmax + (y - yhi) * v.hstep / (f[N - 1] - f[N - 2]);
