@@ -391,6 +391,21 @@ __device__ __forceinline__ int stencil_start(int k, int N) {
 }
 
 
+// Position u = (ln H' - y_0) / dy of ln H' on the grain's inverse-table grid
+// (FP32), and the cubic Hermite of that table at u in node interval j.
+__device__ __forceinline__ float inv_pos_f32(const PlanView& v, int s, float hs) {
+    return (logf(hs) - v.ylof[s]) * v.dyinvf[s];
+}
+
+__device__ __forceinline__ float inv_hermite_f32(const PlanView& v, int s, float u, int j) {
+    const float4 g = v.invf[(int64_t)s * (v.M - 1) + j];
+    const float t = u - (float)j;
+    const float t2 = t * t, t3 = t2 * t;
+    const float lnT = (2.0f * t3 - 3.0f * t2 + 1.0f) * g.x + (t3 - 2.0f * t2 + t) * g.y +
+                      (3.0f * t2 - 2.0f * t3) * g.z + (t3 - t2) * g.w;
+    return expf(lnT);
+}
+
 // ---------------------------------------------------------------------------
 // FP32 mixed solve of Eq. 7: the grain's inverse table ln T(y), y = ln H',
 // as a cubic Hermite in FP32 between the two nodes around y (one 16-byte
@@ -407,16 +422,10 @@ __device__ __forceinline__ int table_lookup_f32(const PlanView& v, int s, float 
         return 0;
     }
     if (hs == 0.0f) { *T = 0.0f; return 0; }
-    const float u = (logf(hs) - v.ylof[s]) * v.dyinvf[s];
-    const float top = (float)(v.M - 1);
-    if (!(u >= 0.0f && u <= top)) return 1;  // outside, or the table is not finite
+    const float u = inv_pos_f32(v, s, hs);
+    if (!(u >= 0.0f && u <= (float)(v.M - 1))) return 1;  // outside, or the table is not finite
     const int j = (int)u < v.M - 2 ? (int)u : v.M - 2;
-    const float4 g = v.invf[(int64_t)s * (v.M - 1) + j];
-    const float t = u - (float)j;
-    const float t2 = t * t, t3 = t2 * t;
-    const float lnT = (2.0f * t3 - 3.0f * t2 + 1.0f) * g.x + (t3 - 2.0f * t2 + t) * g.y +
-                      (3.0f * t2 - 2.0f * t3) * g.z + (t3 - t2) * g.w;
-    *T = expf(lnT);
+    *T = inv_hermite_f32(v, s, u, j);
     return 0;
 }
 
@@ -431,6 +440,25 @@ __device__ __forceinline__ double ln_normal_f32(float x) {
     const float m = __builtin_amdgcn_frexp_mantf(x);
     const int e = __builtin_amdgcn_frexp_expf(x);
     return ((double)e + (double)__builtin_amdgcn_logf(m)) * LN2;
+}
+
+// Position u = (ln H' - y_0) / dy of ln H' on the grain's FP64 inverse-table
+// grid, and the cubic Hermite of that table at u in node interval j, with T
+// leaving in FP32 as e^head (1 + tail) from the FP32 head of ln T.
+__device__ __forceinline__ double inv_pos_f64(const PlanView& v, int s, float hs) {
+    return (ln_normal_f32(hs) - v.ylo[s]) * v.dyinv[s];
+}
+
+__device__ __forceinline__ float inv_hermite_f64(const PlanView& v, int s, double u, int j) {
+    const double2* g = v.invd + (int64_t)s * v.M + j;
+    const double2 g0 = g[0], g1 = g[1];
+    const double t = u - (double)j;
+    const double d = g1.x - g0.x;
+    const double c2 = 3.0 * d - 2.0 * g0.y - g1.y;
+    const double c3 = g0.y + g1.y - 2.0 * d;
+    const double lnT = g0.x + t * (g0.y + t * (c2 + t * c3));
+    const float head = (float)lnT;
+    return expf(head) * (1.0f + (float)(lnT - (double)head));
 }
 
 // ---------------------------------------------------------------------------
@@ -451,19 +479,46 @@ __device__ __forceinline__ int table_lookup_f64(const PlanView& v, int s, float 
     }
     if (hs == 0.0f) { *T = 0.0f; return 0; }
     if (hs < 1.17549435e-38f) return 1;  // subnormal
-    const double u = (ln_normal_f32(hs) - v.ylo[s]) * v.dyinv[s];
+    const double u = inv_pos_f64(v, s, hs);
     if (!(u >= 0.0 && u <= (double)(v.M - 1))) return 1;  // outside, or not finite
     const int j = (int)u < v.M - 2 ? (int)u : v.M - 2;
-    const double2* g = v.invd + (int64_t)s * v.M + j;
-    const double2 g0 = g[0], g1 = g[1];
-    const double t = u - (double)j;
-    const double d = g1.x - g0.x;
-    const double c2 = 3.0 * d - 2.0 * g0.y - g1.y;
-    const double c3 = g0.y + g1.y - 2.0 * d;
-    const double lnT = g0.x + t * (g0.y + t * (c2 + t * c3));
-    const float head = (float)lnT;
-    *T = expf(head) * (1.0f + (float)(lnT - (double)head));
+    *T = inv_hermite_f64(v, s, u, j);
     return 0;
+}
+
+// ---------------------------------------------------------------------------
+// The two lookups above without branches, for kernels that take several pairs
+// per thread: the node loads are made at a clamped index whatever the pair,
+// so that the loads of all the thread's pairs can be in flight together, and
+// the outcome is selected at the end.  *T and the status agree with the
+// branching forms pair for pair (the nonfinite count is left to the caller).
+// ---------------------------------------------------------------------------
+constexpr int LOOKUP_OK = 0, LOOKUP_PENDING = 1, LOOKUP_NONFINITE = 2;
+
+__device__ __forceinline__ int table_lookup_f64_nb(const PlanView& v, int s, float hs, float* T) {
+    const double u = inv_pos_f64(v, s, hs);
+    const bool in = u >= 0.0 && u <= (double)(v.M - 1);
+    const double uc = in ? u : 0.0;
+    const int j = (int)uc < v.M - 2 ? (int)uc : v.M - 2;
+    const float t = inv_hermite_f64(v, s, uc, j);
+    const bool bad = !(hs >= 0.0f) || __builtin_isinf(hs);
+    const bool zero = hs == 0.0f;
+    *T = bad ? __builtin_nanf("") : (zero ? 0.0f : t);
+    return bad ? LOOKUP_NONFINITE
+               : (zero ? LOOKUP_OK
+                       : ((hs < 1.17549435e-38f || !in) ? LOOKUP_PENDING : LOOKUP_OK));
+}
+
+__device__ __forceinline__ int table_lookup_f32_nb(const PlanView& v, int s, float hs, float* T) {
+    const float u = inv_pos_f32(v, s, hs);
+    const bool in = u >= 0.0f && u <= (float)(v.M - 1);
+    const float uc = in ? u : 0.0f;
+    const int j = (int)uc < v.M - 2 ? (int)uc : v.M - 2;
+    const float t = inv_hermite_f32(v, s, uc, j);
+    const bool bad = !(hs >= 0.0f) || __builtin_isinf(hs);
+    const bool zero = hs == 0.0f;
+    *T = bad ? __builtin_nanf("") : (zero ? 0.0f : t);
+    return bad ? LOOKUP_NONFINITE : (zero ? LOOKUP_OK : (!in ? LOOKUP_PENDING : LOOKUP_OK));
 }
 
 // ---------------------------------------------------------------------------

@@ -8,9 +8,10 @@
 // come through the scalar cache.  T goes back through the same LDS slots and
 // leaves with coalesced stores; the Newton evaluations of the block are
 // counted with one atomic.
-// Mixed: one thread per (cell, grain) in row-major order (coalesced H and T),
-// an O(1) lookup in the grain's inverse table ln T(ln H) (a cubic Hermite
-// in FP64 between FP64 nodes, or in FP32 with the FP32 lookup).
+// Mixed: four (cell, grain) pairs per thread, 256 apart in row-major order
+// (coalesced H and T), each an O(1) lookup in the grain's inverse table
+// ln T(ln H) (a cubic Hermite in FP64 between FP64 nodes, or in FP32 with the
+// FP32 lookup), all four in flight together.
 // Table-linear: the same layout, a bracketed search in the grain's table of
 // powers at evenly spaced T and linear interpolation (Sections 2 and 5).
 // Every form adds the optional extra heating Q to H first.
@@ -90,36 +91,73 @@ __global__ __launch_bounds__(256) void solve_table_kernel(PlanView v, int64_t C,
     T[c * ldt + s] = table_linear_T(v, s, h * v.hscale[s], cnt);
 }
 
-// One thread per (cell, grain) in row-major order: coalesced H and T.  Pairs
+// Mixed: each thread takes MIXED_PER pairs 256 apart in row-major order
+// (coalesced H and T) and looks all of them up before it stores any, so that
+// their dependent loads (H, then the grain's inverse-table nodes) overlap: a
+// single lookup per thread leaves the kernel waiting on memory latency.  Pairs
 // outside the table go to an LDS list and are then solved exactly by the
 // block's waves in turn (one pair per wave at a time, lanes over wavelength).
+constexpr int MIXED_PER = 4;
+constexpr int MIXED_BLOCK = 256 * MIXED_PER;  // pairs per workgroup
+
+template <int MODE>
+__device__ __forceinline__ int lookup_status(const PlanView& v, int s, float hs, float* T,
+                                             bool active, dust_counters* cnt) {
+    if constexpr (MODE == MODE_MIXED_POLISH) {
+        if (!active) return LOOKUP_OK;
+        return table_lookup_polish(v, s, hs, T, cnt) != 0 ? LOOKUP_PENDING : LOOKUP_OK;
+    } else if constexpr (MODE == MODE_MIXED_F32) {
+        return table_lookup_f32_nb(v, s, hs, T);
+    } else {
+        return table_lookup_f64_nb(v, s, hs, T);
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void solve_mixed_kernel(PlanView v, int64_t C,
                                                           const float* __restrict__ H,
                                                           int64_t ldh, float* __restrict__ T,
                                                           int64_t ldt, dust_counters* cnt) {
     __shared__ int sCount;
-    __shared__ int sList[256];
+    __shared__ int sList[MIXED_BLOCK];
     if (threadIdx.x == 0) sCount = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool active = i < C * v.S;
-    const int64_t c = active ? i / v.S : 0;
-    const int s = active ? (int)(i - c * v.S) : 0;
-    float h = active ? H[c * ldh + s] : 0.0f;
-    if (active && v.q) h += v.q[c * v.ldq + s];
-    const float hs = h * v.hscale[s];
-    float t = 0.0f;
-    if (active) {
-        if (mixed_lookup<MODE>(v, s, hs, &t, cnt) != 0)
-            sList[atomicAdd(&sCount, 1)] = threadIdx.x;
-        else
-            T[c * ldt + s] = t;
+    const int64_t n = C * v.S;
+    const int64_t base = (int64_t)blockIdx.x * MIXED_BLOCK + threadIdx.x;
+    int64_t c[MIXED_PER];
+    int s[MIXED_PER];
+    float hs[MIXED_PER];
+#pragma unroll
+    for (int k = 0; k < MIXED_PER; ++k) {
+        // past the end, read the last pair again (nothing is stored for it)
+        const int64_t i = (base + k * 256 < n) ? base + k * 256 : n - 1;
+        c[k] = i / v.S;
+        s[k] = (int)(i - c[k] * v.S);
+        float h = H[c[k] * ldh + s[k]];
+        if (v.q) h += v.q[c[k] * v.ldq + s[k]];
+        hs[k] = h * v.hscale[s[k]];
     }
+    float t[MIXED_PER];
+    int st[MIXED_PER];
+#pragma unroll
+    for (int k = 0; k < MIXED_PER; ++k)
+        st[k] = lookup_status<MODE>(v, s[k], hs[k], &t[k], base + k * 256 < n, cnt);
+    int nonfinite = 0;
+#pragma unroll
+    for (int k = 0; k < MIXED_PER; ++k) {
+        if (base + k * 256 >= n) continue;
+        if (st[k] == LOOKUP_PENDING) {
+            sList[atomicAdd(&sCount, 1)] = threadIdx.x + k * 256;
+        } else {
+            nonfinite += st[k] == LOOKUP_NONFINITE;
+            T[c[k] * ldt + s[k]] = t[k];
+        }
+    }
+    if (cnt) wave_count_add(&cnt->n_nonfinite, nonfinite);
     __syncthreads();
-    const int n = sCount;
-    for (int e = threadIdx.x >> 6; e < n; e += blockDim.x >> 6) {
-        const int64_t ip = (int64_t)blockIdx.x * 256 + sList[e];
+    const int np = sCount;
+    for (int e = threadIdx.x >> 6; e < np; e += blockDim.x >> 6) {
+        const int64_t ip = (int64_t)blockIdx.x * MIXED_BLOCK + sList[e];
         const int64_t cp = ip / v.S;
         const int sp = (int)(ip - cp * v.S);
         float hf = H[cp * ldh + sp];
@@ -137,17 +175,16 @@ hipError_t launch_solve(const PlanView& v, int64_t C, const float* H, int64_t ld
     if (C == 0) return hipSuccess;
     if (v.mode == DUST_MIXED) {
         const int64_t n = C * v.S;
+        const unsigned blocks = (unsigned)((n + MIXED_BLOCK - 1) / MIXED_BLOCK);
         if (v.f32_lookup)
             hipLaunchKernelGGL(solve_mixed_kernel<MODE_MIXED_F32>,
-                               dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, C, H, ldh,
-                               T, ldt, cnt);
+                               dim3(blocks), dim3(256), 0, st, v, C, H, ldh, T, ldt, cnt);
         else if (v.polish)
-            hipLaunchKernelGGL(solve_mixed_kernel<MODE_MIXED_POLISH>,
-                               dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, C, H, ldh,
-                               T, ldt, cnt);
+            hipLaunchKernelGGL(solve_mixed_kernel<MODE_MIXED_POLISH>, dim3(blocks), dim3(256), 0,
+                               st, v, C, H, ldh, T, ldt, cnt);
         else
-            hipLaunchKernelGGL(solve_mixed_kernel<DUST_MIXED>, dim3((unsigned)((n + 255) / 256)),
-                               dim3(256), 0, st, v, C, H, ldh, T, ldt, cnt);
+            hipLaunchKernelGGL(solve_mixed_kernel<DUST_MIXED>, dim3(blocks), dim3(256), 0, st, v,
+                               C, H, ldh, T, ldt, cnt);
     } else if (v.mode == DUST_TABLE_LINEAR) {
         const int64_t n = C * v.S;
         hipLaunchKernelGGL(solve_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
