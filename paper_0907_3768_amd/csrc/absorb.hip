@@ -11,8 +11,10 @@
 //                    J_hi K_hi + J_hi K_lo + J_lo K_hi, FP32 accumulation:
 //                    a blocked product of 256 cells x up to 256 grains per
 //                    workgroup with J and the weight fragments staged in LDS
-//                    (absorb_gemm_kernel), or, on a device that cannot give
-//                    one workgroup its 144 KB of LDS, 64 cells per workgroup
+//                    (absorb_dl_kernel: loaded straight into LDS, for J rows
+//                    aligned to 16 bytes; absorb_gemm_kernel: through
+//                    registers), or, on a device that cannot give one
+//                    workgroup its 144 KB of LDS, 64 cells per workgroup
 //                    with the fragments read from L2 (absorb_mb_kernel).
 #include "fused_body.h"
 
@@ -365,12 +367,270 @@ __global__ __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GW / 4,
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same blocked product with J and the weight fragments moved from memory
+// straight into LDS (global_load_lds_dwordx4: no staging registers), J three
+// k-steps deep, so that two k-steps of J (64 KB per CU) are in flight while
+// the MFMAs of a third run; the register-staged form above keeps one (32 KB).
+// J stays FP32 in LDS and each wave splits its own A fragments into bf16 hi
+// and lo after reading them (the same round-to-nearest-even split as above,
+// so H is the same bit for bit).  LDS: 3 x 32 KB of J + the double-buffered
+// fragments (160 KB at 16 tiles).  Needs J rows 16-byte aligned; a ragged
+// last k-step (NL not a multiple of 32) is read from global memory into
+// registers with zeros past NL; rows past C read row C - 1 and are not stored.
+// Stage layout [row block][chunk of 4 wavelengths][row] of float4: a wave's
+// direct load fills one row block's 4 chunks x 16 rows (1 KB, lane l at
+// chunk l / 16, row l mod 16), and a fragment read (lanes 0-15: rows 0-15 of
+// one chunk) touches 256 consecutive bytes.
+// Synchronisation is by hand: every full k-step issues the same loads in the
+// same order (fragments of step + 1, then J of step + 2), so "all but this
+// wave's last two loads landed" (vmcnt(2)) before the barrier means the
+// k-step about to be read is in LDS; the LDS reads are asm statements that
+// wait for themselves, since the compiler would make each read wait for every
+// direct load in flight.
+// ---------------------------------------------------------------------------
+constexpr int D_STAGES = 3;
+typedef __attribute__((address_space(3))) void* lds_ptr;
+typedef float4 JStage[G_CELLS / 16][8][16];  // 32 KB
+
+// vmcnt(n) with lgkmcnt(0): this wave's LDS writes done and all but its last
+// n global loads (the direct loads of the next k-step) landed.
+#define DUST_WAIT_VM2_LGKM0 0x0072
+#define DUST_WAIT_VM0_LGKM0 0x0070
+
+// Two 16-byte LDS reads (at addr + OFF and addr + OFF + GAP) and their wait,
+// as one statement: the compiler would otherwise make every LDS read wait for
+// all the direct loads in flight (it cannot tell the stages apart), which
+// would undo the pipeline.  The offsets are immediates, so a wave needs one
+// address register per array.
+template <int OFF, int GAP, typename T>
+__device__ __forceinline__ void lds_read2(uint32_t addr, T& a, T& b) {
+    static_assert(OFF >= 0 && OFF + GAP < 65536, "16-bit LDS offset");
+    asm volatile(
+        "ds_read_b128 %0, %2 offset:%3\n\t"
+        "ds_read_b128 %1, %2 offset:%4\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(a), "=&v"(b)
+        : "v"(addr), "i"(OFF), "i"(OFF + GAP));
+}
+template <typename T>
+__device__ __forceinline__ uint32_t lds_addr(T* p) {
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) T*)p;
+}
+// f(integral_constant<int, I>) for I = B .. E - 1, unrolled at compile time
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GW / 4, GW / 4))) void absorb_dl_kernel(
+    PlanView v, int64_t C, const float* __restrict__ J, int64_t ldj, float* __restrict__ H,
+    int64_t ldh) {
+    __shared__ __align__(16) JStage sJ0, sJ1, sJ2;        // 96 KB
+    __shared__ __align__(16) bf16x8 sB[2][NT][2][64];     // up to 64 KB
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kq = lane >> 4;
+    const int t0 = (int)blockIdx.y * NT;
+    const int nt = __builtin_amdgcn_readfirstlane(min(NT, v.Sp / 16 - t0));
+    const int nsteps = v.NLp / 32;
+    const int nfull = v.NL / 32;  // k-steps with every wavelength inside NL
+    const int64_t c0 = (int64_t)blockIdx.x * G_CELLS;
+    // J mover: wave w fills row block w (GW = 16 row blocks of 16 cells); a
+    // k-step past the last full one re-reads that one into a stage nobody
+    // reads again, so that every k-step issues the same two loads last
+    const int64_t dcell = c0 + 16 * wave + row;
+    const float* drow = J + (dcell < C ? dcell : C - 1) * ldj + 4 * kq;
+    auto next_j = [&](int step, JStage& dst) {
+        const int sj = step < nfull ? step : nfull - 1;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            __builtin_amdgcn_global_load_lds(drow + sj * 32 + 16 * i,
+                                             (lds_ptr)&dst[wave][4 * i][0], 16, 0, 0);
+    };
+    // fragment mover: the plan's fragment (tile t, plane pl) of a k-step is
+    // 64 x 16 bytes in lane order, one direct load into sB[buf][t][pl];
+    // fragment p = wave + 16 j of the 2 NT goes to tile p / 2, plane p mod 2
+    constexpr int PW = (2 * NT + GW - 1) / GW;
+    auto next_k = [&](int step, int buf) {
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const int p = wave + GW * j;
+            const int t = p >> 1, pl = p & 1;
+            if (p < 2 * NT && t < nt) {
+                const int64_t o = (((int64_t)(t0 + t) * nsteps + step) * 64 + lane) * 8;
+                __builtin_amdgcn_global_load_lds((pl ? v.klo : v.khi) + o,
+                                                 (lds_ptr)&sB[buf][t][pl][0], 16, 0, 0);
+            }
+        }
+    };
+    // wave layout: WC cell groups x WGR grain groups, each wave MBW row blocks
+    // x TW tiles (16 tiles: 32 cells x 128 grains; 64 x 64, a fifth fewer LDS
+    // bytes per MFMA but twice the splits per J value, measured 5 % slower)
+    constexpr int WGR = NT >= 6 ? 2 : 1;
+    constexpr int WC = GW / WGR;
+    constexpr int MBW = 16 / WC;
+    constexpr int TW = NT / WGR;
+    static_assert(TW * WGR == NT, "tiles split evenly over grain groups");
+    const int cg = wave % WC, gg = wave / WC;
+    f32x4 acc[MBW][TW];
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+        for (int t = 0; t < TW; ++t) acc[mb][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // bf16 hi and lo of the wave's J values (row `row`, wavelengths 8 kq ..
+    // 8 kq + 7 of a k-step) of row block mb
+    // (two values per v_cvt_pk_bf16_f32, the hi parts back to FP32 by shift
+    // and mask: the same round-to-nearest-even split as element by element,
+    // in three instructions per value instead of four)
+    auto split = [&](const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        u32x4 h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float a = x[2 * e], b = x[2 * e + 1];
+            const uint32_t hp =
+                __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+            const f32x2 r = {a - __uint_as_float(hp << 16), b - __uint_as_float(hp & 0xffff0000u)};
+            h[e] = hp;
+            l[e] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+        }
+        hi = __builtin_bit_cast(bf16x8, h);
+        lo = __builtin_bit_cast(bf16x8, l);
+    };
+    // the MFMAs of one k-step from the split J and fragment buffer buf; the
+    // wave's fragments of tile t sit at b0 + 2 KB t (hi) and + 1 KB (lo)
+    const uint32_t b0 = lds_addr(&sB[0][TW * gg][0][lane]);
+    constexpr uint32_t BUF_BYTES = sizeof(bf16x8) * NT * 2 * 64;
+    auto mfmas = [&](const bf16x8 (&ahi)[MBW], const bf16x8 (&alo)[MBW], int buf) {
+        const uint32_t bb = b0 + (buf ? BUF_BYTES : 0u);
+        bf16x8 bhi[2], blo[2];
+        lds_read2<0, 1024>(bb, bhi[0], blo[0]);
+        static_for<0, TW>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+#pragma unroll
+            for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+                for (int mb = 0; mb < MBW; ++mb)
+                    acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        pr == 2 ? alo[mb] : ahi[mb], pr == 1 ? blo[t & 1] : bhi[t & 1],
+                        acc[mb][t], 0, 0, 0);
+            if constexpr (t + 1 < TW)  // the next tile's fragments while these MFMAs run
+                lds_read2<2048 * (t + 1), 1024>(bb, bhi[(t + 1) & 1], blo[(t + 1) & 1]);
+        });
+    };
+    // a bare barrier (a fenced one would also wait for the loads in flight);
+    // the empty asm statements keep the compiler's memory accesses on their side
+    auto barrier = [&]() {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+    // one full k-step: J of `step` in cur; fragments of step + 1 and J of
+    // step + 2 are issued (in that order) before its MFMAs
+    auto substep = [&](int step, JStage& cur, JStage& nxt2) {
+        __builtin_amdgcn_s_waitcnt(DUST_WAIT_VM2_LGKM0);  // all but step + 1's J loads
+        barrier();
+        if (step + 1 < nsteps) next_k(step + 1, (step + 1) & 1);
+        next_j(step + 2, nxt2);  // the stage every wave finished reading before the barrier
+        // the wave's J of row block MBW cg + mb: at a0 + 2 KB mb and + 256 B
+        const uint32_t a0 = lds_addr(&cur[MBW * cg][2 * kq][row]);
+        bf16x8 ahi[MBW], alo[MBW];
+        static_for<0, MBW>([&](auto mc) {
+            constexpr int mb = decltype(mc)::value;
+            f32x4 p, q;
+            lds_read2<2048 * mb, 256>(a0, p, q);
+            const float x[8] = {p[0], p[1], p[2], p[3], q[0], q[1], q[2], q[3]};
+            split(x, ahi[mb], alo[mb]);
+        });
+        mfmas(ahi, alo, step & 1);
+    };
+    next_k(0, 0);
+    if (nfull > 0) {
+        next_j(0, sJ0);
+        next_j(1, sJ1);
+        int step = 0;
+        for (; step + 3 <= nfull; step += 3) {
+            substep(step, sJ0, sJ2);
+            substep(step + 1, sJ1, sJ0);
+            substep(step + 2, sJ2, sJ1);
+        }
+        if (step < nfull) substep(step, sJ0, sJ2);
+        if (step + 1 < nfull) substep(step + 1, sJ1, sJ0);
+    }
+    __builtin_amdgcn_s_waitcnt(DUST_WAIT_VM0_LGKM0);  // no load into LDS outlives this point
+    if (nfull < nsteps) {  // the ragged last k-step: J straight from global, zeros past NL
+        barrier();
+        bf16x8 ahi[MBW], alo[MBW];
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb) {
+            const int64_t c = c0 + 16 * (MBW * cg + mb) + row;
+            const int k = nfull * 32 + 8 * kq;
+            const float* src = J + (c < C ? c : 0) * ldj + k;
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = (c < C && k + e < v.NL) ? src[e] : 0.0f;
+            split(x, ahi[mb], alo[mb]);
+        }
+        mfmas(ahi, alo, nfull & 1);
+    }
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+        const int s = 16 * (t0 + TW * gg + t) + row;
+        if (TW * gg + t < nt && s < v.S) {
+            const float hinv = v.hinv[s];
+#pragma unroll
+            for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t c = c0 + 16 * (MBW * cg + mb) + 4 * kq + r;
+                    if (c < C) H[c * ldh + s] = acc[mb][t][r] * hinv;
+                }
+        }
+    }
+}
+
+// LDS the current device gives one workgroup (asked once per device; 0 if
+// unknown).
+int lds_per_block() {
+    static int cached[64];  // 0 unknown, else bytes + 1
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!cached[dev]) {
+        int lds = 0;
+        (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        cached[dev] = lds + 1;
+    }
+    return cached[dev] - 1;
+}
+
+// Whether one workgroup can hold the register-staged blocked kernel's 144 KB,
+// or the direct-load kernel's 160 KB (at 16 tiles).
+bool gemm_fits() {
+    return (size_t)lds_per_block() >=
+           sizeof(__bf16) * 2 * 2 * G_CELLS * G_ROW + sizeof(bf16x8) * 2 * G_NT * 2 * 64;
+}
+bool dl_fits() {
+    return (size_t)lds_per_block() >=
+           sizeof(float4) * D_STAGES * G_CELLS * 8 + sizeof(bf16x8) * 2 * G_NT * 2 * 64;
+}
+
 template <int NT>
 hipError_t launch_gemm(const PlanView& v, int64_t C, const float* J, int64_t ldj, float* H,
                        int64_t ldh, hipStream_t st) {
     const dim3 grid((unsigned)((C + G_CELLS - 1) / G_CELLS), (unsigned)((v.Sp / 16 + NT - 1) / NT));
     const uintptr_t a = (uintptr_t)J;
-    if ((a & 15u) == 0 && (ldj & 3) == 0)
+    if ((a & 15u) == 0 && (ldj & 3) == 0 && dl_fits())
+        hipLaunchKernelGGL((absorb_dl_kernel<NT>), grid, dim3(64 * GW), 0, st, v, C, J, ldj, H,
+                           ldh);
+    else if ((a & 15u) == 0 && (ldj & 3) == 0)
         hipLaunchKernelGGL((absorb_gemm_kernel<NT, 4>), grid, dim3(64 * GW), 0, st, v, C, J, ldj, H,
                            ldh);
     else if ((a & 7u) == 0 && (ldj & 1) == 0)
@@ -380,23 +640,6 @@ hipError_t launch_gemm(const PlanView& v, int64_t C, const float* J, int64_t ldj
         hipLaunchKernelGGL((absorb_gemm_kernel<NT, 1>), grid, dim3(64 * GW), 0, st, v, C, J, ldj, H,
                            ldh);
     return hipGetLastError();
-}
-
-// Whether the current device gives one workgroup the blocked kernel's
-// 144 KB of LDS (asked once per device).
-bool gemm_fits() {
-    static int cached[64];  // 0 unknown, 1 yes, 2 no
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
-    if (!cached[dev]) {
-        int lds = 0;
-        (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        cached[dev] = (size_t)lds >= sizeof(__bf16) * 2 * 2 * G_CELLS * G_ROW +
-                                         sizeof(bf16x8) * 2 * G_NT * 2 * 64
-                          ? 1
-                          : 2;
-    }
-    return cached[dev] == 1;
 }
 
 template <int NTW>

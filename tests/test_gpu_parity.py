@@ -585,7 +585,13 @@ ABSORB_SHAPES = [(257, 100, [0], 5, 100, 0),       # float4 rows, 5 grains, 257 
                  (515, 250, [0, 1], 40, 253, 0),   # odd rows: scalar loads
                  (129, 200, [0, 1], 40, 204, 2),   # rows aligned to 8 bytes only
                  (70, 64, [0, 1, 2], 100, 64, 0),  # 300 grains: two passes (16 + 3 tiles)
-                 (40, 96, [0, 1], 512, 96, 0)]     # 1024 grains: four passes
+                 (40, 96, [0, 1], 512, 96, 0),     # 1024 grains: four passes
+                 # float4 rows, by the number of full 32-wavelength k-steps
+                 (100, 20, [0], 30, 20, 0),        # none (NL < 32), 2 tiles
+                 (300, 32, [0, 1], 40, 32, 0),     # one, 5 tiles
+                 (600, 133, [0, 1, 2], 40, 136, 0),  # four + a ragged one, 8 tiles, 600 cells
+                 (260, 160, [0, 1], 90, 160, 0),   # five, 12 tiles
+                 (513, 192, [0, 1, 2], 80, 192, 0)]  # six, 15 of 16 tiles, 513 cells
 
 
 @pytest.mark.parametrize("n_cells,n_lambda,species,n_sizes,ldj,off", ABSORB_SHAPES)
