@@ -372,8 +372,9 @@ __global__ __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GW / 4,
 // straight into LDS (global_load_lds_dwordx4: no staging registers), J three
 // k-steps deep, so that two k-steps of J (64 KB per CU) are in flight while
 // the MFMAs of a third run; the register-staged form above keeps one (32 KB).
-// J stays FP32 in LDS and each wave splits its own A fragments into bf16 hi
-// and lo after reading them (the same round-to-nearest-even split as above,
+// J lands in LDS as FP32; the wave that loaded a row block splits it in
+// place into bf16 hi and lo before the k-step's barrier, once per value for
+// all the waves that read it (the same round-to-nearest-even split as above,
 // so H is the same bit for bit).  LDS: 3 x 32 KB of J + the double-buffered
 // fragments (160 KB at 16 tiles).  Needs J rows 16-byte aligned; a ragged
 // last k-step (NL not a multiple of 32) is read from global memory into
@@ -412,6 +413,18 @@ __device__ __forceinline__ void lds_read2(uint32_t addr, T& a, T& b) {
         "s_waitcnt lgkmcnt(0)"
         : "=&v"(a), "=&v"(b)
         : "v"(addr), "i"(OFF), "i"(OFF + GAP));
+}
+// Two 16-byte LDS writes (at addr + OFF and addr + OFF + GAP) and their wait.
+template <int OFF, int GAP, typename T>
+__device__ __forceinline__ void lds_write2(uint32_t addr, const T& a, const T& b) {
+    static_assert(OFF >= 0 && OFF + GAP < 65536, "16-bit LDS offset");
+    asm volatile(
+        "ds_write_b128 %0, %1 offset:%3\n\t"
+        "ds_write_b128 %0, %2 offset:%4\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        :
+        : "v"(addr), "v"(a), "v"(b), "i"(OFF), "i"(OFF + GAP)
+        : "memory");
 }
 template <typename T>
 __device__ __forceinline__ uint32_t lds_addr(T* p) {
@@ -537,18 +550,28 @@ __global__ __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GW / 4,
     // step + 2 are issued (in that order) before its MFMAs
     auto substep = [&](int step, JStage& cur, JStage& nxt2) {
         __builtin_amdgcn_s_waitcnt(DUST_WAIT_VM2_LGKM0);  // all but step + 1's J loads
+        {
+            // split the row block this wave loaded, in place, once for all the
+            // waves that read it: the 8 values of (row, chunks 2 kq and
+            // 2 kq + 1) become their bf16 hi (in chunk 2 kq) and lo (in chunk
+            // 2 kq + 1), where the operand reads below find them
+            const uint32_t own = lds_addr(&cur[wave][2 * kq][row]);
+            f32x4 p, q;
+            lds_read2<0, 256>(own, p, q);
+            const float x[8] = {p[0], p[1], p[2], p[3], q[0], q[1], q[2], q[3]};
+            bf16x8 hi, lo;
+            split(x, hi, lo);
+            lds_write2<0, 256>(own, hi, lo);
+        }
         barrier();
         if (step + 1 < nsteps) next_k(step + 1, (step + 1) & 1);
         next_j(step + 2, nxt2);  // the stage every wave finished reading before the barrier
-        // the wave's J of row block MBW cg + mb: at a0 + 2 KB mb and + 256 B
+        // the wave's split J of row block MBW cg + mb: hi at a0 + 2 KB mb, lo + 256 B
         const uint32_t a0 = lds_addr(&cur[MBW * cg][2 * kq][row]);
         bf16x8 ahi[MBW], alo[MBW];
         static_for<0, MBW>([&](auto mc) {
             constexpr int mb = decltype(mc)::value;
-            f32x4 p, q;
-            lds_read2<2048 * mb, 256>(a0, p, q);
-            const float x[8] = {p[0], p[1], p[2], p[3], q[0], q[1], q[2], q[3]};
-            split(x, ahi[mb], alo[mb]);
+            lds_read2<2048 * mb, 256>(a0, ahi[mb], alo[mb]);
         });
         mfmas(ahi, alo, step & 1);
     };
