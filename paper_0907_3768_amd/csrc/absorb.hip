@@ -484,7 +484,7 @@ __global__ __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GW / 4,
     };
     // wave layout: WC cell groups x WGR grain groups, each wave MBW row blocks
     // x TW tiles (16 tiles: 32 cells x 128 grains; 64 x 64, a fifth fewer LDS
-    // bytes per MFMA but twice the splits per J value, measured 5 % slower)
+    // bytes per MFMA, measured the same)
     constexpr int WGR = NT >= 6 ? 2 : 1;
     constexpr int WC = GW / WGR;
     constexpr int MBW = 16 / WC;
