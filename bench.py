@@ -622,6 +622,25 @@ def run_alu_probe():
     return 0
 
 
+def run_stage(args, torch, pm, J, m, H, T, L, cnt, C, NL, S, name):
+    """One call of the mixed three-launch path timed alone (`--stage`), with
+    the algorithmic HBM bytes of that call: J read and H written (absorb), H
+    read and T written (solve), T and m read and L written (emit)."""
+    pm.prepare()
+    pm.absorb(J, H)
+    pm.solve(H, T, counters=cnt)
+    torch.cuda.synchronize()
+    fn, nbytes = {"absorb": (lambda: pm.absorb(J, H), 4.0 * (C * NL + C * S)),
+                  "solve": (lambda: pm.solve(H, T, counters=cnt), 8.0 * C * S),
+                  "emit": (lambda: pm.emit(T, m, L), 4.0 * (C * S + C + C * NL))}[args.stage]
+    _, k = time_steps(torch, [(args.stage, fn)], args.steps, args.warmup)
+    ms = k[args.stage]
+    print(json.dumps({"stage": args.stage, "workload": name, "ms": ms, "steps": args.steps,
+                      "algorithmic_bytes": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
+                      "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -644,6 +663,10 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline form (for kernel-trace statistics of its "
                          "kernel alone); no secondary forms and no CPU baseline")
+    ap.add_argument("--stage", choices=("absorb", "solve", "emit"), default=None,
+                    help="only time one call of the mixed three-launch path (dust_absorb, "
+                         "dust_solve_T or dust_emit_sed) on the workload, for kernel traces "
+                         "and counters of its kernel alone")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 launches), to "
                          "calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes")
@@ -713,6 +736,8 @@ def main():
     torch.cuda.synchronize()
 
     pm = dust.Plan(grid, "mixed")
+    if args.stage:
+        return run_stage(args, torch, pm, J, m, H, T, L, cnt, C, NL, S, w.name)
     pp = dust.Plan(grid, "plain")
 
     mixed_stages = [("prepare", lambda: pm.prepare()),
