@@ -594,6 +594,26 @@ ABSORB_SHAPES = [(257, 100, [0], 5, 100, 0),       # float4 rows, 5 grains, 257 
                  (513, 192, [0, 1, 2], 80, 192, 0)]  # six, 15 of 16 tiles, 513 cells
 
 
+@pytest.mark.parametrize("n_cells,n_lambda,ldj,species,n_sizes", [
+    (300, 256, 256, [0, 1], 40),      # direct loads into LDS, eight full k-steps, 5 tiles
+    (513, 200, 204, [0, 1, 2], 80),   # direct loads, six full k-steps + a ragged one, 15 tiles
+    (257, 250, 250, [0, 1], 40),      # rows aligned to 8 bytes: staged through registers
+    (70, 64, 64, [0, 1, 2], 100)])    # 300 grains: two passes
+def test_absorb_matches_fused_heating(dev, n_cells, n_lambda, ldj, species, n_sizes):
+    """dust_absorb followed by dust_solve_T gives the fused kernel's T bit for
+    bit (mixed form): both heating kernels run the same bf16 split and the
+    same MFMA products in the same order, and both solves the same lookup."""
+    g = synth.make_species_grid(n_lambda, species, n_sizes)
+    say(f"absorb vs fused C={n_cells} NL={n_lambda} ldj={ldj} S={g.n_grains}")
+    J, m = _inputs(g, n_cells, 910 + n_cells, dev, ldj=ldj)
+    plan = dust.Plan(g, "mixed")
+    T_f, _ = plan.fused(J, m)
+    H = plan.absorb(J)
+    T_s = plan.solve(H)
+    torch.cuda.synchronize()
+    assert torch.equal(T_s, T_f)
+
+
 @pytest.mark.parametrize("n_cells,n_lambda,species,n_sizes,ldj,off", ABSORB_SHAPES)
 def test_absorb_load_widths_and_passes(dev, n_cells, n_lambda, species, n_sizes, ldj, off):
     """dust_absorb in the mixed form against the oracle's Eq. 6 on every row,
