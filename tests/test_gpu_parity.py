@@ -591,7 +591,9 @@ ABSORB_SHAPES = [(257, 100, [0], 5, 100, 0),       # float4 rows, 5 grains, 257 
                  (300, 32, [0, 1], 40, 32, 0),     # one, 5 tiles
                  (600, 133, [0, 1, 2], 40, 136, 0),  # four + a ragged one, 8 tiles, 600 cells
                  (260, 160, [0, 1], 90, 160, 0),   # five, 12 tiles
-                 (513, 192, [0, 1, 2], 80, 192, 0)]  # six, 15 of 16 tiles, 513 cells
+                 (513, 192, [0, 1, 2], 80, 192, 0),  # six, 15 of 16 tiles, 513 cells
+                 (1, 64, [0], 5, 64, 0),           # a single cell: 255 rows of the block past C
+                 (17, 96, [0, 1], 40, 100, 0)]     # three full k-steps, no ragged one, padded rows
 
 
 @pytest.mark.parametrize("n_cells,n_lambda,ldj,species,n_sizes", [
