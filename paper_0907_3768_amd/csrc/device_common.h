@@ -305,23 +305,22 @@ __device__ __forceinline__ double expm1_pos(double x) {
 
 // ---------------------------------------------------------------------------
 // Exact FP64 power of grain s at T and T dP/dT (Eq. 7's right side), summed
-// over wavelengths by the whole wave: lane i takes wavelengths i, i+64, ...;
-// a butterfly reduction leaves both totals in every lane.  Every lane of the
-// wave must call it with the same (s, T).  The wavelengths increase, so x =
-// c2 / (lam T) falls with l: a 64-wavelength chunk whose last x is past the
-// overflow point of e^x holds only exact zero terms and is skipped (cold
-// grains skip the short half of the grid; the sums are unchanged bit for bit).
+// over wavelengths by the whole wave: lane i takes wavelengths i, i+64, ...
+// from l0 (a multiple of 64) on; a butterfly reduction leaves both totals in
+// every lane.  Every lane of the wave must call it with the same (s, T, l0).
+// The wavelengths below l0 must hold only terms that are exactly zero at T
+// (see exact_first_chunk), so the sums are those over the whole grid.
 // ---------------------------------------------------------------------------
-__device__ inline void wave_power_f64(const PlanView& v, int s, double T, double* P, double* D) {
+__device__ inline void wave_power_f64(const PlanView& v, int s, double T, int l0, double* P,
+                                      double* D) {
     const int lane = threadIdx.x & 63;
     const double* kdb = v.kdb + (int64_t)s * v.NL;
     const double invT = rcp_f64(T);
     double p = 0.0, d = 0.0;
-#pragma unroll 1
-    for (int l0 = 0; l0 < v.NL; l0 += 64) {
-        const int last = (l0 + 63 < v.NL) ? l0 + 63 : v.NL - 1;
-        if (v.c2l[last] * invT > EXP_F64_OVERFLOW) continue;  // every e^x overflows
-        const int l = l0 + lane;
+    // (no test per chunk: the loads of successive chunks can be in flight together)
+#pragma unroll 2
+    for (int c0 = l0; c0 < v.NL; c0 += 64) {
+        const int l = c0 + lane;
         if (l < v.NL) {
             const double x = v.c2l[l] * invT;
             const double em = expm1_pos(x);
@@ -340,6 +339,25 @@ __device__ inline void wave_power_f64(const PlanView& v, int s, double T, double
     *D = d;
 }
 
+// First wavelength (a multiple of 64) from which the exact power at any
+// T <= Thi can hold a nonzero term.  The wavelengths increase, so x =
+// c2 / (lam T) falls with l, and a 64-wavelength chunk whose last x is past
+// the overflow point of e^x (with a margin of 1 for the rounding of T) holds
+// only terms that are exactly zero: skipping such chunks leaves the sums
+// unchanged bit for bit (cold grains skip the short half of the grid).  A
+// binary search over the chunks, once per pair.
+__device__ inline int exact_first_chunk(const PlanView& v, double Thi) {
+    const double invT = rcp_f64(Thi);
+    int a = 0, b = (v.NL + 63) >> 6;  // the answer lies in [a, b]
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        const int last = (64 * mid + 63 < v.NL) ? 64 * mid + 63 : v.NL - 1;
+        if (v.c2l[last] * invT > EXP_F64_OVERFLOW + 1.0) a = mid + 1;
+        else b = mid;
+    }
+    return 64 * a;
+}
+
 // Exact FP64 solve of Eq. 7 for one pair, by the whole wave (uniform
 // arguments): Newton on ln P = ln H in ln T from lnT0, safeguarded by the
 // bracket [lnlo, lnhi].  Used by the mixed path for pairs outside the table.
@@ -348,9 +366,11 @@ __device__ inline double wave_solve_exact_f64(const PlanView& v, int s, double h
     const double lnH = ln_f32_value(hs, v.lntab);
     double lo = lnlo, hi = lnhi;
     double lnT = (lnT0 > lo && lnT0 < hi) ? lnT0 : 0.5 * (lo + hi);
+    // every iterate stays at or below the bracket's top
+    const int l0 = exact_first_chunk(v, exp_f64(lnhi));
     for (int it = 0; it < 100; ++it) {
         double P, D;
-        wave_power_f64(v, s, exp_f64(lnT), &P, &D);
+        wave_power_f64(v, s, exp_f64(lnT), l0, &P, &D);
         double next;
         if (!(P > 0.0 && P < __builtin_inf())) {
             if (P > 0.0) hi = lnT; else lo = lnT;  // inf: T far too high; 0: far too low
