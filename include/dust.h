@@ -176,7 +176,10 @@ dust_status dust_plan_prepare(dust_plan* plan, void* stream);
 dust_status dust_plan_info(const dust_plan* plan, int32_t* n_lambda,
                            int32_t* n_grains, int32_t* mode);
 
-/* Eq. 6 (Section 4.2): H[c*ldh + s] for c < n_cells, s < S, FP32 output. */
+/* Eq. 6 (Section 4.2): H[c*ldh + s] for c < n_cells, s < S, FP32 output.
+ * Any 4-byte aligned J is accepted; J 16-byte aligned with ldj a multiple of
+ * 4 (every row 16-byte aligned) takes the fastest form, which loads J
+ * straight into on-chip memory. */
 dust_status dust_absorb(dust_plan* plan, int64_t n_cells,
                         const float* J, int64_t ldj,
                         float* H, int64_t ldh, void* stream);
