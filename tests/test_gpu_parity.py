@@ -596,6 +596,45 @@ ABSORB_SHAPES = [(257, 100, [0], 5, 100, 0),       # float4 rows, 5 grains, 257 
                  (17, 96, [0, 1], 40, 100, 0)]     # three full k-steps, no ragged one, padded rows
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_random_shapes_three_launches(dev, seed):
+    """dust_absorb -> dust_solve_T -> dust_emit_sed (mixed) on seeded random
+    shapes -- cells 1-700, 8-300 wavelengths, 1-3 species of 1-60 sizes, J
+    rows aligned to 16, 8 or 4 bytes by the row length and the start offset
+    (so every J load width and both blocked heating kernels) -- against the
+    oracle on every row, with nothing written past the rows."""
+    rng = np.random.default_rng(4200 + seed)
+    C = int(rng.integers(1, 701))
+    NL = int(rng.integers(8, 301))
+    species = sorted(rng.choice(3, size=int(rng.integers(1, 4)), replace=False).tolist())
+    nz = int(rng.integers(1, 61))
+    # J rows 16-byte aligned (direct loads into LDS), 8-byte, or 4-byte
+    align = (4, 2, 1)[seed % 3]
+    pad = (-NL) % align + align * int(rng.integers(0, 3))
+    off = {4: 0, 2: 2 * int(rng.integers(0, 2)), 1: 1}[align]
+    g = synth.make_species_grid(NL, species, nz)
+    S = g.n_grains
+    say(f"random seed={seed}: C={C} NL={NL} species={species} sizes={nz} pad={pad} off={off}")
+    p = synth.cell_params(C, 5100 + seed)
+    ldj = NL + pad
+    buf = torch.full((C * ldj + off + 8,), -7.0, dtype=torch.float32, device=dev)
+    J = buf[off:off + C * ldj].view(C, ldj)[:, :NL]
+    synth.radiation_field(p, g.lam, device=dev, out=J)
+    m = torch.as_tensor(p.m_dust, dtype=torch.float32, device=dev)
+    plan = dust.Plan(g, "mixed")
+    Hbuf = torch.full((C, S + 2), -9.0, dtype=torch.float32, device=dev)
+    Tbuf = torch.full((C, S + 3), -3.0, dtype=torch.float32, device=dev)
+    Lbuf = torch.full((C, NL + 5), -5.0, dtype=torch.float32, device=dev)
+    H, T, L = Hbuf[:, :S], Tbuf[:, :S], Lbuf[:, :NL]
+    plan.absorb(J, H)
+    plan.solve(H, T)
+    plan.emit(T, m, L)
+    torch.cuda.synchronize()
+    assert torch.all(Hbuf[:, S:] == -9.0) and torch.all(Tbuf[:, S:] == -3.0)
+    assert torch.all(Lbuf[:, NL:] == -5.0)
+    check_against_oracle(g, _host(J), _host(m).astype(np.float64), _host(T), _host(L), _host(H))
+
+
 @pytest.mark.parametrize("n_cells,n_lambda,ldj,species,n_sizes", [
     (300, 256, 256, [0, 1], 40),      # direct loads into LDS, eight full k-steps, 5 tiles
     (513, 200, 204, [0, 1, 2], 80),   # direct loads, six full k-steps + a ragged one, 15 tiles
