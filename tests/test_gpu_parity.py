@@ -596,10 +596,11 @@ ABSORB_SHAPES = [(257, 100, [0], 5, 100, 0),       # float4 rows, 5 grains, 257 
                  (17, 96, [0, 1], 40, 100, 0)]     # three full k-steps, no ragged one, padded rows
 
 
+@pytest.mark.parametrize("path", ["separate", "fused"])
 @pytest.mark.parametrize("seed", range(12))
-def test_random_shapes_three_launches(dev, seed):
-    """dust_absorb -> dust_solve_T -> dust_emit_sed (mixed) on seeded random
-    shapes -- cells 1-700, 8-300 wavelengths, 1-3 species of 1-60 sizes, J
+def test_random_shapes_three_launches(dev, seed, path):
+    """dust_absorb -> dust_solve_T -> dust_emit_sed, and dust_run_fused
+    (mixed), on seeded random shapes -- cells 1-700, 8-300 wavelengths, 1-3 species of 1-60 sizes, J
     rows aligned to 16, 8 or 4 bytes by the row length and the start offset
     (so every J load width and both blocked heating kernels) -- against the
     oracle on every row, with nothing written past the rows."""
@@ -626,13 +627,17 @@ def test_random_shapes_three_launches(dev, seed):
     Tbuf = torch.full((C, S + 3), -3.0, dtype=torch.float32, device=dev)
     Lbuf = torch.full((C, NL + 5), -5.0, dtype=torch.float32, device=dev)
     H, T, L = Hbuf[:, :S], Tbuf[:, :S], Lbuf[:, :NL]
-    plan.absorb(J, H)
-    plan.solve(H, T)
-    plan.emit(T, m, L)
+    if path == "separate":
+        plan.absorb(J, H)
+        plan.solve(H, T)
+        plan.emit(T, m, L)
+    else:
+        plan.fused(J, m, T, L)
     torch.cuda.synchronize()
     assert torch.all(Hbuf[:, S:] == -9.0) and torch.all(Tbuf[:, S:] == -3.0)
     assert torch.all(Lbuf[:, NL:] == -5.0)
-    check_against_oracle(g, _host(J), _host(m).astype(np.float64), _host(T), _host(L), _host(H))
+    check_against_oracle(g, _host(J), _host(m).astype(np.float64), _host(T), _host(L),
+                         _host(H) if path == "separate" else None)
 
 
 @pytest.mark.parametrize("n_cells,n_lambda,ldj,species,n_sizes", [
